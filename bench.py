@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Benchmark of the positional population count on one MI355X.
+
+A step is one pass of the whole path over the workload: one pospopcnt16 call
+over a single stream of 2^33 uint16 words (16 GiB, each bit Bernoulli(1/2)),
+resident in HBM before timing starts, adding into 16 uint64 counters.
+
+Prints one JSON line: input GB/s of the timed steps, the roofline of the
+counting kernel (achieved algorithmic bytes / its average launch duration,
+measured with HIP events on the stream it runs on, against 8 TB/s HBM), the
+read-only ceiling kernel on the same buffer, and the CPU oracle timed on a
+bounded sample of the same input.  After timing, the counts are checked:
+the total equals (warmup + steps) times one pass, and the GPU counts of the
+sample equal the oracle's.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1911_02696_amd import inputs as I  # noqa: E402
+
+HBM_PEAK_GBPS = 8000.0
+SEED = I.BASE_SEED
+
+# name -> (k, n words, distribution, description)
+WORKLOADS = {
+    "u16-2^33": (16, 1 << 33, I.Dist.uniform(),
+                 "single pospopcnt16 stream, 2^33 uint16 words (16 GiB), Bernoulli(0.5) bits"),
+    "u16-2^30": (16, 1 << 30, I.Dist.uniform(), "pospopcnt16, 2^30 uint16 words (2 GiB)"),
+    "u16-2^31": (16, 1 << 31, I.Dist.uniform(), "pospopcnt16, 2^31 uint16 words (4 GiB)"),
+    "u16-2^32": (16, 1 << 32, I.Dist.uniform(), "pospopcnt16, 2^32 uint16 words (8 GiB)"),
+    "u8-2^28": (8, 1 << 28, I.Dist.uniform(), "pospopcnt8, 2^28 uint8 words (256 MiB)"),
+    "u16-2^28": (16, 1 << 28, I.Dist.uniform(), "pospopcnt16, 2^28 uint16 words (512 MiB)"),
+    "u32-2^28": (32, 1 << 28, I.Dist.uniform(), "pospopcnt32, 2^28 uint32 words (1 GiB)"),
+    "u8-2^33": (8, 1 << 34, I.Dist.uniform(), "pospopcnt8, 2^34 uint8 words (16 GiB)"),
+    "u32-2^32": (32, 1 << 32, I.Dist.uniform(), "pospopcnt32, 2^32 uint32 words (16 GiB)"),
+    "u16-2^20": (16, 1 << 20, I.Dist.uniform(), "pospopcnt16, 2^20 uint16 words (2 MiB)"),
+}
+DEFAULT_WORKLOAD = "u16-2^33"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("ppc_single.hip", "ppc_device.h"):
+        with open(os.path.join(ROOT, "paper_1911_02696_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_tag: str, workload: str, src_hash: str, per_launch_algo_bytes: int):
+    """HBM bytes per launch from the committed PMC summary of this kernel and
+    workload, if the summary was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel_tag}_{workload.replace('^', '')}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        m = re.match(r"^\s*([a-z_0-9]+)\s*[:=]\s*([0-9a-fx.eE+-]+)\s*$", line.strip())
+        if m:
+            vals[m.group(1)] = m.group(2)
+    if vals.get("kernel_source_sha256") != src_hash:
+        return None
+    try:
+        fetch = float(vals["fetch_kib_per_dispatch"]) * 1024 * float(vals.get("fetch_scale", 1))
+        write = float(vals["write_kib_per_dispatch"]) * 1024 * float(vals.get("write_scale", 1))
+    except KeyError:
+        return None
+    return {"hbm_bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+            "vs_algorithmic": (fetch + write) / per_launch_algo_bytes, "source": os.path.relpath(path, ROOT)}
+
+
+def upload(dev, nbytes, dist, seed, chunk=1 << 30):
+    import torch
+    pinned = torch.empty(min(chunk, nbytes), dtype=torch.uint8).pin_memory()
+    pn = pinned.numpy()
+    for first in range(0, nbytes, chunk):
+        m = min(chunk, nbytes - first)
+        I.fill(pn[:m], dist, seed, first_byte=first)
+        dev[first:first + m].copy_(pinned[:m], non_blocking=False)
+
+
+def cpu_baseline(k, dist, seed, target_s: float, max_bytes: int):
+    """The oracle on the first S bytes of the same input, S sized for ~target_s of
+    wall time on all host threads; returns (report, counts of the sample)."""
+    import oracle
+    threads = I.default_threads()
+    probe = 64 << 20
+    host = I.generate(probe, dist, seed)
+    t0 = time.perf_counter()
+    oracle.count(host, probe // (k // 8), k, threads=threads)
+    rate = probe / max(time.perf_counter() - t0, 1e-6)
+    s = int(min(max_bytes, max(probe, rate * target_s)))
+    s -= s % (1 << 20)
+    host = I.generate(s, dist, seed)
+    times = []
+    for _ in range(1):
+        t0 = time.perf_counter()
+        counts = oracle.count(host, s // (k // 8), k, threads=threads)
+        times.append(time.perf_counter() - t0)
+    used = oracle.get().threads_used
+    dt = min(times)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    rep = {"value": round(s / dt / 1e9, 4), "unit": "GB/s", "cores": used, "kind": "oracle",
+           "sample": f"first {s} bytes ({s // (k // 8)} words) of the same input, "
+                     f"{used} threads, {dt:.2f} s", "cpu": model}
+    return rep, counts, s
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--variant", default="csa", choices=["csa", "ballot"])
+    ap.add_argument("--depth", type=int, default=0)
+    ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ceiling", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(the count shards by byte range with one 256-byte sum per GPU, which this "
+              "build does not run).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1911_02696_amd import api
+
+    k, n, dist, desc = WORKLOADS[args.workload]
+    nbytes = n * (k // 8)
+    torch.cuda.set_device(0)
+    info = api.device_info()
+    free, _ = torch.cuda.mem_get_info()
+    if free < nbytes + (256 << 20):
+        print(f"workload needs {nbytes / 2**30:.1f} GiB, {free / 2**30:.1f} GiB free",
+              file=sys.stderr)
+        sys.exit(3)
+    print(f"[bench] {desc}: uploading {nbytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
+    dev = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    upload(dev, nbytes, dist, SEED + 2)
+    counts = torch.zeros(k, dtype=torch.int64, device="cuda")
+    cfg = dict(variant=args.variant, depth=args.depth, block_threads=args.block_threads,
+               blocks_per_cu=args.blocks_per_cu)
+    stream = torch.cuda.current_stream()
+
+    one = api.pospopcnt(dev, k, n=n, **cfg)  # one pass, for the consistency check
+    for _ in range(args.warmup):
+        api.pospopcnt(dev, k, n=n, out=counts, **cfg)
+    torch.cuda.synchronize()
+
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        api.pospopcnt(dev, k, n=n, out=counts, **cfg)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]) / 1e3
+    avg_kernel = float(ev[0].elapsed_time(ev[-1]) / 1e3 / args.steps)
+    ms_per_step = wall / args.steps * 1e3
+
+    total = counts.cpu().numpy()
+    one_np = one.cpu().numpy()
+    ok_total = bool((total == one_np * (args.warmup + args.steps)).all())
+
+    ceiling = None
+    if not args.no_ceiling:
+        sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for _ in range(args.warmup):
+            api.read_ceiling(dev, sink=sink, depth=args.depth)
+        cev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        cev[0].record(stream)
+        for _ in range(args.steps):
+            api.read_ceiling(dev, sink=sink, depth=args.depth)
+        cev[1].record(stream)
+        torch.cuda.synchronize()
+        c_avg = cev[0].elapsed_time(cev[1]) / 1e3 / args.steps
+        ceiling = {"kernel": "ceiling_kernel (XOR of the same loads)",
+                   "gbps": round(nbytes / c_avg / 1e9, 1),
+                   "frac_of_peak": round(nbytes / c_avg / 1e9 / HBM_PEAK_GBPS, 4)}
+
+    cpu = None
+    ok_sample = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu, sample_counts, s = cpu_baseline(k, dist, SEED + 2, args.cpu_seconds, nbytes)
+        g = api.pospopcnt(dev, k, n=s // (k // 8), **cfg).cpu().numpy()
+        ok_sample = bool((g == sample_counts.astype(np.int64)).all())
+
+    achieved = nbytes / avg_kernel / 1e9
+    src_hash = kernel_source_hash()
+    kname = {"csa": "csa_kernel", "ballot": "ballot_kernel"}[args.variant]
+    traffic = read_traffic(args.variant, args.workload, src_hash, nbytes)
+    value = nbytes / (wall / args.steps) / 1e9
+    line = {
+        "metric": "pospopcnt16 input GB/s (single stream)" if k == 16 else
+                  f"pospopcnt{k} input GB/s (single stream)",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16" if k == 16 else f"u{k}",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "k": k, "n_words": n,
+                   "bytes": nbytes, "offset": 0, "variant": args.variant,
+                   "depth": args.depth or None, "parallelism": "single GPU"},
+        "words_per_s": round(n / (wall / args.steps), 1),
+        "frac_of_hbm_peak": round(value / HBM_PEAK_GBPS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic, "kernel": kname,
+                     "algorithmic_bytes_per_launch": nbytes,
+                     "avg_launch_ms": round(avg_kernel * 1e3, 4),
+                     "min_launch_ms": round(float(per.min()) * 1e3, 4),
+                     "kernel_source_sha256": src_hash},
+        "ceiling": ceiling,
+        "cpu_baseline": cpu,
+        "check": {"total_equals_passes_times_one_pass": ok_total,
+                  "sample_equals_oracle": ok_sample},
+        "device": {"name": info["name"], "arch": info["arch"], "cus": info["compute_units"],
+                   "clock_mhz": info["clock_khz"] / 1000},
+    }
+    print(json.dumps(line), flush=True)
+    if not ok_total or ok_sample is False:
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,132 @@
+/*
+ * pospopcnt.h -- C ABI of the MI355X (gfx950) positional population count.
+ *
+ * Operation (Klarqvist, Mula, Lemire, "Efficient Computation of Positional
+ * Population Counts Using SIMD Instructions", abstract, Sec. 1 and Sec. 4,
+ * Fig. 3): given n words of k bits, counts[p] += number of words whose bit p is
+ * set, for p = 0 .. k-1.  For one-hot words the k sums are a frequency
+ * histogram (Sec. 1, Table 1).
+ *
+ * Conventions shared by every entry point:
+ *   - Word j of a stream at byte address ptr is the k/8 bytes at ptr + j*k/8,
+ *     least significant byte first.  ptr may be any byte address.
+ *   - Counts are 64-bit and are ADDED INTO (the paper's counters start at zero
+ *     and are only incremented, Sec. 4, Fig. 3): zero them for a fresh count.
+ *     Splitting a stream into pieces and counting each piece into the same
+ *     counts gives the count of the whole stream.
+ *   - Input and counts live in device memory (hipMalloc or equivalent); the
+ *     caller owns them.  Unless stated otherwise no call allocates memory.
+ *   - Calls are asynchronous on `stream` (a hipStream_t, NULL = null stream):
+ *     arguments are validated synchronously, and on any error nothing is
+ *     launched and a status is returned.  Faults inside a kernel surface at the
+ *     caller's next synchronisation, as usual in HIP.
+ *   - n = 0 returns PPC_OK and launches nothing.
+ *   - Calls on distinct streams may be made from several host threads.
+ *   - Results are exact integers: identical on every run and for every launch
+ *     configuration.
+ */
+#ifndef POSPOPCNT_H
+#define POSPOPCNT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A hipStream_t passed as an opaque pointer; NULL is the null stream. */
+typedef void* ppc_stream;
+
+/* Status codes returned by every entry point. */
+enum {
+    PPC_OK = 0,
+    PPC_ERR_NULL = 1,     /* a required pointer is NULL (input or counts with n > 0) */
+    PPC_ERR_ALIGN = 2,    /* counts (or a descriptor array) not 8-byte aligned */
+    PPC_ERR_WIDTH = 3,    /* k is not 8, 16 or 32 */
+    PPC_ERR_RANGE = 4,    /* n * k / 8 does not fit in 64 bits */
+    PPC_ERR_HIP = 5,      /* a HIP runtime call failed: see ppc_last_hip_error() */
+    PPC_ERR_BUDGET = 6,   /* serving: request larger than the memory budget */
+    PPC_ERR_ARG = 7,      /* another argument is out of range (configuration, size) */
+    PPC_ERR_OVERLAP = 8,  /* counts overlaps the input bytes */
+    PPC_ERR_STATE = 9     /* object used in a state that does not allow the call */
+};
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char* ppc_status_string(int status);
+
+/* The hipError_t of the last failed HIP call made by this library on the
+ * calling host thread (0 if none). */
+int ppc_last_hip_error(void);
+
+/* ------------------------------------------------------------------------
+ * Single stream.
+ *
+ * pospopcnt_u8 / _u16 / _u32: counts has 8 / 16 / 32 entries.
+ *   ptr    device pointer to n*k/8 bytes, any alignment; may be NULL if n = 0.
+ *   n      number of k-bit words (64-bit: inputs of 2^32 words and more are
+ *          allowed, unlike the paper's uint32_t length, Fig. 3).
+ *   counts device pointer, 8-byte aligned, k uint64 entries, added into; must
+ *          not overlap the input.  Several concurrent calls may add into the
+ *          same counts (the kernels flush with 64-bit device-scope atomics).
+ * Errors: PPC_ERR_NULL, PPC_ERR_ALIGN, PPC_ERR_RANGE, PPC_ERR_OVERLAP,
+ * PPC_ERR_HIP (launch failure).  Nothing is launched on error.
+ * The work is the Harley-Seal carry-save-adder method of Sec. 4.1 (circuits of
+ * Sec. 2), with the carry counted per bit position as in Fig. 6.
+ * ---------------------------------------------------------------------- */
+int pospopcnt_u8(const void* ptr, uint64_t n, uint64_t* counts, ppc_stream stream);
+int pospopcnt_u16(const void* ptr, uint64_t n, uint64_t* counts, ppc_stream stream);
+int pospopcnt_u32(const void* ptr, uint64_t n, uint64_t* counts, ppc_stream stream);
+
+/* Same, with the width k in {8, 16, 32} as an argument (PPC_ERR_WIDTH otherwise). */
+int pospopcnt(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stream stream);
+
+/* Kernel variants. */
+enum {
+    PPC_VARIANT_CSA = 0,     /* per-lane Harley-Seal circuit + masked popcount (Sec. 4.1) */
+    PPC_VARIANT_BALLOT = 1   /* wave-wide bit transposition: ballot per bit, popcount */
+};
+
+/* Launch configuration for pospopcnt_ex.  Zero in any field selects the
+ * library's default for that field. */
+typedef struct {
+    int32_t variant;        /* PPC_VARIANT_CSA or PPC_VARIANT_BALLOT */
+    int32_t depth;          /* CSA: inputs per lane per circuit, 8, 16 or 32 dwords
+                               (the 2^N-input circuits of Sec. 2; the paper's 256 B /
+                               512 B / 1 kB circuits are N = 2, 3, 4) */
+    int32_t block_threads;  /* 64 .. 1024, multiple of 64 */
+    int32_t blocks_per_cu;  /* resident blocks per compute unit used to size the grid */
+    int64_t grid;           /* explicit number of blocks (overrides blocks_per_cu) */
+} ppc_launch_config;
+
+/* pospopcnt with an explicit launch configuration (NULL = defaults).  Same
+ * contract and errors as pospopcnt, plus PPC_ERR_ARG for a field out of range.
+ * Every configuration gives the same counts. */
+int pospopcnt_ex(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stream stream,
+                 const ppc_launch_config* config);
+
+/* Read-only bandwidth reference: reads the nbytes at ptr (any alignment) with
+ * the same loads, tiling and grid as the CSA kernel, XOR-reduces them, and
+ * XORs the result into *sink (device, 8-byte aligned).  It computes no count;
+ * it measures the memory ceiling the counting kernels run against.
+ * config: NULL or as for pospopcnt_ex (depth sets loads per lane). */
+int ppc_read_ceiling(const void* ptr, uint64_t nbytes, uint64_t* sink, ppc_stream stream,
+                     const ppc_launch_config* config);
+
+/* Device facts used to size launches (for the current HIP device). */
+typedef struct {
+    int32_t device;
+    int32_t compute_units;
+    int32_t clock_khz;
+    int32_t l2_bytes;
+    int64_t global_mem_bytes;
+    char name[64];
+    char arch[64];
+} ppc_device_info;
+
+int ppc_get_device_info(ppc_device_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POSPOPCNT_H */

@@ -1,0 +1,115 @@
+"""ctypes loader of libpospopcnt.so (the C ABI of include/pospopcnt.h).
+
+There is no fallback: if the library is missing the import of any entry point
+raises, naming the build command.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpospopcnt.so")
+
+PPC_OK = 0
+STATUS_NAMES = {
+    0: "PPC_OK", 1: "PPC_ERR_NULL", 2: "PPC_ERR_ALIGN", 3: "PPC_ERR_WIDTH",
+    4: "PPC_ERR_RANGE", 5: "PPC_ERR_HIP", 6: "PPC_ERR_BUDGET", 7: "PPC_ERR_ARG",
+    8: "PPC_ERR_OVERLAP", 9: "PPC_ERR_STATE",
+}
+VARIANT_CSA, VARIANT_BALLOT = 0, 1
+
+
+class PpcError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        lib = _lib_or_none()
+        msg = lib.ppc_status_string(status).decode() if lib else STATUS_NAMES.get(status, "?")
+        if status == 5 and lib:
+            msg += f" (hipError_t {lib.ppc_last_hip_error()})"
+        super().__init__(f"{what}: {msg}" if what else msg)
+
+
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("grid", ctypes.c_int64)]
+
+
+class DeviceInfo(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("compute_units", ctypes.c_int32),
+                ("clock_khz", ctypes.c_int32), ("l2_bytes", ctypes.c_int32),
+                ("global_mem_bytes", ctypes.c_int64), ("name", ctypes.c_char * 64),
+                ("arch", ctypes.c_char * 64)]
+
+
+_vp, _u64, _i32, _i64 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64
+
+# name -> (restype, argtypes); every entry point the binding uses.
+SIGNATURES = {
+    "ppc_status_string": (ctypes.c_char_p, [_i32]),
+    "ppc_last_hip_error": (_i32, []),
+    "pospopcnt_u8": (_i32, [_vp, _u64, _vp, _vp]),
+    "pospopcnt_u16": (_i32, [_vp, _u64, _vp, _vp]),
+    "pospopcnt_u32": (_i32, [_vp, _u64, _vp, _vp]),
+    "pospopcnt": (_i32, [_vp, _u64, _i32, _vp, _vp]),
+    "pospopcnt_ex": (_i32, [_vp, _u64, _i32, _vp, _vp, ctypes.POINTER(LaunchConfig)]),
+    "ppc_read_ceiling": (_i32, [_vp, _u64, _vp, _vp, ctypes.POINTER(LaunchConfig)]),
+    "ppc_get_device_info": (_i32, [ctypes.POINTER(DeviceInfo)]),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+def _lib_or_none():
+    return _lib
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(
+                    f"{LIB_PATH} is missing: build it with "
+                    "`python -m paper_1911_02696_amd.build` (hipcc, gfx950)")
+            handle = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(handle, name)
+                fn.restype = res
+                fn.argtypes = args
+            _extend(handle)
+            _lib = handle
+    return _lib
+
+
+_extensions = []
+
+
+def register_signatures(table: dict):
+    """Add signatures of further entry points (used by the batch and serving modules)."""
+    _extensions.append(table)
+    if _lib is not None:
+        _apply(_lib, table)
+
+
+def _apply(handle, table):
+    for name, (res, args) in table.items():
+        fn = getattr(handle, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+def _extend(handle):
+    for table in _extensions:
+        _apply(handle, table)
+
+
+def check(status: int, what: str = ""):
+    if status != PPC_OK:
+        raise PpcError(status, what)

@@ -1,0 +1,128 @@
+"""Python binding of the single-stream entry points (argument marshalling only).
+
+torch supplies device memory and the stream; every step of the count runs in
+the library's HIP kernels.  Counts are returned in int64 storage, which holds
+the same bits as the library's uint64 counters for any total below 2^63.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+from ._lib import LaunchConfig, PpcError, check
+
+VARIANTS = {"csa": L.VARIANT_CSA, "ballot": L.VARIANT_BALLOT}
+
+
+def stream_handle(stream=None) -> int:
+    """A hipStream_t as an int: torch's current stream when stream is None."""
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def launch_config(variant="csa", depth=0, block_threads=0, blocks_per_cu=0, grid=0):
+    if isinstance(variant, str):
+        if variant not in VARIANTS:
+            raise ValueError(f"variant must be one of {sorted(VARIANTS)}")
+        variant = VARIANTS[variant]
+    return LaunchConfig(variant, depth, block_threads, blocks_per_cu, grid)
+
+
+def _device_bytes(x: torch.Tensor, byte_offset: int) -> int:
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise ValueError("input must be a tensor in GPU memory")
+    if not x.is_contiguous():
+        raise ValueError("input must be contiguous")
+    avail = x.numel() * x.element_size() - byte_offset
+    if byte_offset < 0 or avail < 0:
+        raise ValueError("byte_offset outside the tensor")
+    return avail
+
+
+def _counts_tensor(out, k, device):
+    if out is None:
+        return torch.zeros(k, dtype=torch.int64, device=device)
+    if out.dtype not in (torch.int64, torch.uint64) or out.numel() != k:
+        raise ValueError(f"out must hold {k} int64 counters")
+    if not out.is_contiguous() or out.device != device:
+        raise ValueError("out must be contiguous and on the input's device")
+    return out
+
+
+def pospopcnt_ptr(ptr: int, n: int, k: int, counts_ptr: int, stream=None, config=None) -> None:
+    """Raw call: counts_ptr[p] += count of bit p over n k-bit words at device address ptr."""
+    cfg = ctypes.byref(config) if config is not None else None
+    check(L.lib().pospopcnt_ex(ptr or None, n, k, counts_ptr or None, stream_handle(stream), cfg),
+          f"pospopcnt(k={k}, n={n})")
+
+
+def pospopcnt(x: torch.Tensor, k: int, n: int | None = None, byte_offset: int = 0,
+              out: torch.Tensor | None = None, stream=None, **config) -> torch.Tensor:
+    """Positional population count of n k-bit little-endian words that start
+    byte_offset bytes into x's memory (x: any dtype, read as bytes).
+
+    Adds into `out` (k int64 counters on x's device; zeros when None) and returns it.
+    Keyword arguments select a launch configuration (variant='csa'|'ballot', depth,
+    block_threads, blocks_per_cu, grid); every configuration gives the same counts."""
+    if k not in (8, 16, 32):
+        raise ValueError("k must be 8, 16 or 32")
+    avail = _device_bytes(x, byte_offset)
+    if n is None:
+        n = avail // (k // 8)
+    if n < 0 or n * (k // 8) > avail:
+        raise ValueError(f"{n} words of {k} bits do not fit in {avail} bytes")
+    out = _counts_tensor(out, k, x.device)
+    cfg = launch_config(**config) if config else None
+    with torch.cuda.device(x.device):
+        pospopcnt_ptr(x.data_ptr() + byte_offset, n, k, out.data_ptr(), stream, cfg)
+    return out
+
+
+def pospopcnt_u8(x, n=None, byte_offset=0, out=None, stream=None):
+    return pospopcnt(x, 8, n, byte_offset, out, stream)
+
+
+def pospopcnt_u16(x, n=None, byte_offset=0, out=None, stream=None):
+    return pospopcnt(x, 16, n, byte_offset, out, stream)
+
+
+def pospopcnt_u32(x, n=None, byte_offset=0, out=None, stream=None):
+    return pospopcnt(x, 32, n, byte_offset, out, stream)
+
+
+def read_ceiling(x: torch.Tensor, nbytes: int | None = None, byte_offset: int = 0,
+                 sink: torch.Tensor | None = None, stream=None, **config) -> torch.Tensor:
+    """Read-only bandwidth reference: XOR of all (zero-padded, aligned) dwords of the
+    byte range, XORed into sink[0] (an int64 on the device)."""
+    avail = _device_bytes(x, byte_offset)
+    nbytes = avail if nbytes is None else nbytes
+    if nbytes > avail:
+        raise ValueError("range outside the tensor")
+    if sink is None:
+        sink = torch.zeros(1, dtype=torch.int64, device=x.device)
+    cfg = launch_config(**config) if config else None
+    with torch.cuda.device(x.device):
+        check(L.lib().ppc_read_ceiling(x.data_ptr() + byte_offset, nbytes, sink.data_ptr(),
+                                       stream_handle(stream),
+                                       ctypes.byref(cfg) if cfg is not None else None),
+              "ppc_read_ceiling")
+    return sink
+
+
+def device_info() -> dict:
+    info = L.DeviceInfo()
+    check(L.lib().ppc_get_device_info(ctypes.byref(info)), "ppc_get_device_info")
+    return {"device": info.device, "compute_units": info.compute_units,
+            "clock_khz": info.clock_khz, "l2_bytes": info.l2_bytes,
+            "global_mem_bytes": info.global_mem_bytes, "name": info.name.decode(),
+            "arch": info.arch.decode()}
+
+
+__all__ = ["pospopcnt", "pospopcnt_u8", "pospopcnt_u16", "pospopcnt_u32", "pospopcnt_ptr",
+           "read_ceiling", "device_info", "launch_config", "stream_handle", "PpcError",
+           "LaunchConfig"]

@@ -1,0 +1,121 @@
+// ppc_api.hip -- status codes, argument checks, stream splitting, device facts.
+#include <string.h>
+
+#include <mutex>
+
+#include "ppc_internal.h"
+
+namespace ppc {
+
+static thread_local int g_last_hip = 0;
+
+int fail_hip(hipError_t e) {
+    g_last_hip = (int)e;
+    return PPC_ERR_HIP;
+}
+
+int current_device(const DeviceFacts** out) {
+    static std::mutex mu;
+    static DeviceFacts facts[64];
+    int dev = 0;
+    PPC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return PPC_ERR_ARG;
+    std::lock_guard<std::mutex> lock(mu);
+    DeviceFacts& f = facts[dev];
+    if (f.device != dev) {
+        hipDeviceProp_t prop;
+        PPC_HIP(hipGetDeviceProperties(&prop, dev));
+        f.cus = prop.multiProcessorCount;
+        f.clock_khz = prop.clockRate;
+        f.l2_bytes = prop.l2CacheSize;
+        f.global_mem = (int64_t)prop.totalGlobalMem;
+        strncpy(f.name, prop.name, sizeof(f.name) - 1);
+        strncpy(f.arch, prop.gcnArchName, sizeof(f.arch) - 1);
+        f.device = dev;
+    }
+    *out = &f;
+    return PPC_OK;
+}
+
+Split split_stream(const void* ptr, uint64_t nbytes, int k) {
+    const uintptr_t p = (uintptr_t)ptr, end = p + nbytes;
+    const uintptr_t a0 = (p + 15) & ~(uintptr_t)15;
+    Split s;
+    s.rot = 8u * (uint32_t)(p % (uintptr_t)(k / 8));
+    s.head = (const uint8_t*)ptr;
+    if (a0 >= end) {  // fits before the first 16-byte boundary
+        s.head_len = (uint32_t)nbytes;
+        s.body = (const void*)a0;
+        s.units = 0;
+        s.tail = (const uint8_t*)end;
+        s.tail_len = 0;
+        return s;
+    }
+    const uintptr_t a1 = end & ~(uintptr_t)15;
+    s.head_len = (uint32_t)(a0 - p);
+    s.body = (const void*)a0;
+    s.units = (uint64_t)(a1 - a0) / 16;
+    s.tail = (const uint8_t*)a1;
+    s.tail_len = (uint32_t)(end - a1);
+    return s;
+}
+
+int check_stream_args(const void* ptr, uint64_t n, int k, const uint64_t* counts,
+                      uint64_t* nbytes_out) {
+    if (k != 8 && k != 16 && k != 32) return PPC_ERR_WIDTH;
+    *nbytes_out = 0;
+    if (n == 0) return PPC_OK;
+    const uint64_t wb = (uint64_t)(k / 8);
+    if (n > UINT64_MAX / wb) return PPC_ERR_RANGE;
+    const uint64_t nbytes = n * wb;
+    if (!ptr || !counts) return PPC_ERR_NULL;
+    if ((uintptr_t)counts & 7u) return PPC_ERR_ALIGN;
+    const uintptr_t p = (uintptr_t)ptr;
+    if (p + nbytes < p) return PPC_ERR_RANGE;
+    const uintptr_t c0 = (uintptr_t)counts, c1 = c0 + 8u * (uintptr_t)k;
+    if (c0 < p + nbytes && p < c1) return PPC_ERR_OVERLAP;
+    *nbytes_out = nbytes;
+    return PPC_OK;
+}
+
+}  // namespace ppc
+
+using namespace ppc;
+
+extern "C" {
+
+const char* ppc_status_string(int status) {
+    switch (status) {
+    case PPC_OK: return "PPC_OK";
+    case PPC_ERR_NULL: return "PPC_ERR_NULL: required pointer is NULL";
+    case PPC_ERR_ALIGN: return "PPC_ERR_ALIGN: counts or descriptors not 8-byte aligned";
+    case PPC_ERR_WIDTH: return "PPC_ERR_WIDTH: word width must be 8, 16 or 32";
+    case PPC_ERR_RANGE: return "PPC_ERR_RANGE: byte length overflows 64 bits";
+    case PPC_ERR_HIP: return "PPC_ERR_HIP: a HIP runtime call failed";
+    case PPC_ERR_BUDGET: return "PPC_ERR_BUDGET: request exceeds the memory budget";
+    case PPC_ERR_ARG: return "PPC_ERR_ARG: argument out of range";
+    case PPC_ERR_OVERLAP: return "PPC_ERR_OVERLAP: counts overlaps the input";
+    case PPC_ERR_STATE: return "PPC_ERR_STATE: call not allowed in the object's state";
+    default: return "unknown pospopcnt status";
+    }
+}
+
+int ppc_last_hip_error(void) { return g_last_hip; }
+
+int ppc_get_device_info(ppc_device_info* info) {
+    if (!info) return PPC_ERR_NULL;
+    const DeviceFacts* f = nullptr;
+    int st = current_device(&f);
+    if (st) return st;
+    memset(info, 0, sizeof(*info));
+    info->device = f->device;
+    info->compute_units = f->cus;
+    info->clock_khz = f->clock_khz;
+    info->l2_bytes = f->l2_bytes;
+    info->global_mem_bytes = f->global_mem;
+    memcpy(info->name, f->name, sizeof(info->name));
+    memcpy(info->arch, f->arch, sizeof(info->arch));
+    return PPC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// ppc_internal.h -- host-side helpers shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pospopcnt.h"
+
+namespace ppc {
+
+// Remember a failed HIP call for ppc_last_hip_error() and map it to a status.
+int fail_hip(hipError_t e);
+
+#define PPC_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return ::ppc::fail_hip(e_); \
+    } while (0)
+
+struct DeviceFacts {
+    int device = -1;
+    int cus = 0;
+    int clock_khz = 0;
+    int l2_bytes = 0;
+    int64_t global_mem = 0;
+    char name[64] = {0};
+    char arch[64] = {0};
+};
+
+// Facts of the current device (cached per device id).  Returns PPC_OK or an error.
+int current_device(const DeviceFacts** out);
+
+// Byte-range split of a stream: a head before the first 16-byte boundary, a
+// 16-byte aligned body of `units` dwordx4 units, and a tail after the last one.
+struct Split {
+    const uint8_t* head;  // first head byte (== ptr)
+    const uint8_t* tail;  // first tail byte
+    uint32_t head_len;    // 0 .. 15
+    uint32_t tail_len;    // 0 .. 15
+    const void* body;     // 16-byte aligned
+    uint64_t units;       // body length / 16
+    uint32_t rot;         // 8 * (ptr mod (k/8)): dword bit i is word bit (i - rot) mod k
+};
+
+Split split_stream(const void* ptr, uint64_t nbytes, int k);
+
+// Argument checks common to the single-stream entry points.
+int check_stream_args(const void* ptr, uint64_t n, int k, const uint64_t* counts,
+                      uint64_t* nbytes_out);
+
+// Launch configuration after defaults and validation.
+struct Launch {
+    int variant;
+    int logd;      // circuit of 2^logd dwords per lane per step
+    int threads;   // block size
+    int64_t grid;  // blocks
+};
+
+int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has_edges,
+                   uint64_t nbytes, Launch* out);
+
+}  // namespace ppc

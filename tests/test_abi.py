@@ -1,0 +1,128 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/*.h declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1911_02696_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INCLUDE = os.path.join(ROOT, "include")
+
+
+def declared_functions():
+    names = set()
+    for fn in sorted(os.listdir(INCLUDE)):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(INCLUDE, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        text = re.sub(r"typedef[^;]*;", "", text)  # function-pointer typedefs
+        for m in re.finditer(r"\b([A-Za-z_]\w*)\s*\([^;{}]*\)\s*;", text):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail(f"{L.LIB_PATH} not built: run python -m paper_1911_02696_amd.build")
+    return L.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for must in ("pospopcnt_u8", "pospopcnt_u16", "pospopcnt_u32", "pospopcnt",
+                 "ppc_status_string"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = sorted(declared_functions() - exported)
+    assert not missing, f"declared but not exported: {missing}"
+
+
+def test_binding_covers_every_declared_symbol(lib):
+    import paper_1911_02696_amd.api  # noqa: F401  (registers its signatures)
+    known = set(L.SIGNATURES)
+    for table in L._extensions:
+        known |= set(table)
+    missing = sorted(declared_functions() - known)
+    assert not missing, f"no Python signature for: {missing}"
+
+
+def test_status_strings(lib):
+    for code, name in L.STATUS_NAMES.items():
+        assert lib.ppc_status_string(code).decode().startswith(name)
+    assert b"unknown" in lib.ppc_status_string(12345)
+
+
+@pytest.mark.parametrize("k", [0, 1, 7, 12, 24, 64, -8])
+def test_bad_width(lib, k):
+    assert lib.pospopcnt(0x1000, 4, k, 0x8000, None) == 3  # PPC_ERR_WIDTH
+
+
+def test_zero_length_is_a_no_op(lib):
+    # n = 0: OK without touching pointers or launching (NULL pointers allowed)
+    for fn in (lib.pospopcnt_u8, lib.pospopcnt_u16, lib.pospopcnt_u32):
+        assert fn(None, 0, None, None) == 0
+    assert lib.pospopcnt(None, 0, 16, None, None) == 0
+
+
+def test_null_pointers(lib):
+    assert lib.pospopcnt(None, 5, 16, 0x8000, None) == 1
+    assert lib.pospopcnt(0x1000, 5, 16, None, None) == 1
+
+
+def test_misaligned_counts(lib):
+    for off in range(1, 8):
+        assert lib.pospopcnt(0x1000, 5, 16, 0x8000 + off, None) == 2
+
+
+def test_counts_overlapping_input(lib):
+    # input [0x1000, 0x1000 + 100) ; counts of 16 x 8 bytes
+    assert lib.pospopcnt(0x1000, 50, 16, 0x1000 + 96, None) == 8
+    assert lib.pospopcnt(0x1000, 50, 16, 0x1000 - 8 * 16 + 8, None) == 8
+    # adjacent ranges do not overlap; the call then needs a device and fails with
+    # a HIP error here (no GPU in this check), never with an overlap status
+    assert lib.pospopcnt(0x1000, 50, 16, 0x1000 + 104, None) in (0, 5)
+
+
+def test_length_overflow(lib):
+    assert lib.pospopcnt(0x1000, 2**63, 16, 0x8, None) == 4
+    assert lib.pospopcnt(0x1000, 2**62, 32, 0x8, None) == 4
+    assert lib.pospopcnt(2**64 - 64, 100, 8, 0x8, None) == 4  # address wraps
+
+
+def test_bad_launch_config(lib):
+    bad = [L.LaunchConfig(variant=7), L.LaunchConfig(depth=12), L.LaunchConfig(depth=64),
+           L.LaunchConfig(block_threads=96), L.LaunchConfig(block_threads=512),
+           L.LaunchConfig(block_threads=32), L.LaunchConfig(blocks_per_cu=-1),
+           L.LaunchConfig(grid=-5)]
+    for cfg in bad:
+        st = lib.pospopcnt_ex(0x1000, 64, 16, 0x80000, None, ctypes.byref(cfg))
+        # configuration checks run before the device is queried
+        assert st == 7, (cfg.variant, cfg.depth, cfg.block_threads, st)
+
+
+def test_ceiling_arguments(lib):
+    assert lib.ppc_read_ceiling(None, 0, None, None, None) == 0
+    assert lib.ppc_read_ceiling(None, 10, 0x8000, None, None) == 1
+    assert lib.ppc_read_ceiling(0x1000, 10, 0x8003, None, None) == 2
+
+
+def test_no_device_reports_hip_error(lib):
+    """With no GPU the first call that needs the device fails as PPC_ERR_HIP."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    info = L.DeviceInfo()
+    assert lib.ppc_get_device_info(ctypes.byref(info)) == 5
+    assert lib.ppc_last_hip_error() != 0
