@@ -35,19 +35,19 @@ SEED = I.BASE_SEED
 
 # name -> (k, n words, distribution, description)
 WORKLOADS = {
-    "u16-2^33": (16, 1 << 33, I.Dist.uniform(),
+    "u16_2p33": (16, 1 << 33, I.Dist.uniform(),
                  "single pospopcnt16 stream, 2^33 uint16 words (16 GiB), Bernoulli(0.5) bits"),
-    "u16-2^30": (16, 1 << 30, I.Dist.uniform(), "pospopcnt16, 2^30 uint16 words (2 GiB)"),
-    "u16-2^31": (16, 1 << 31, I.Dist.uniform(), "pospopcnt16, 2^31 uint16 words (4 GiB)"),
-    "u16-2^32": (16, 1 << 32, I.Dist.uniform(), "pospopcnt16, 2^32 uint16 words (8 GiB)"),
-    "u8-2^28": (8, 1 << 28, I.Dist.uniform(), "pospopcnt8, 2^28 uint8 words (256 MiB)"),
-    "u16-2^28": (16, 1 << 28, I.Dist.uniform(), "pospopcnt16, 2^28 uint16 words (512 MiB)"),
-    "u32-2^28": (32, 1 << 28, I.Dist.uniform(), "pospopcnt32, 2^28 uint32 words (1 GiB)"),
-    "u8-2^33": (8, 1 << 34, I.Dist.uniform(), "pospopcnt8, 2^34 uint8 words (16 GiB)"),
-    "u32-2^32": (32, 1 << 32, I.Dist.uniform(), "pospopcnt32, 2^32 uint32 words (16 GiB)"),
-    "u16-2^20": (16, 1 << 20, I.Dist.uniform(), "pospopcnt16, 2^20 uint16 words (2 MiB)"),
+    "u16_2p30": (16, 1 << 30, I.Dist.uniform(), "pospopcnt16, 2^30 uint16 words (2 GiB)"),
+    "u16_2p31": (16, 1 << 31, I.Dist.uniform(), "pospopcnt16, 2^31 uint16 words (4 GiB)"),
+    "u16_2p32": (16, 1 << 32, I.Dist.uniform(), "pospopcnt16, 2^32 uint16 words (8 GiB)"),
+    "u8_2p28": (8, 1 << 28, I.Dist.uniform(), "pospopcnt8, 2^28 uint8 words (256 MiB)"),
+    "u16_2p28": (16, 1 << 28, I.Dist.uniform(), "pospopcnt16, 2^28 uint16 words (512 MiB)"),
+    "u32_2p28": (32, 1 << 28, I.Dist.uniform(), "pospopcnt32, 2^28 uint32 words (1 GiB)"),
+    "u8_2p34": (8, 1 << 34, I.Dist.uniform(), "pospopcnt8, 2^34 uint8 words (16 GiB)"),
+    "u32_2p32": (32, 1 << 32, I.Dist.uniform(), "pospopcnt32, 2^32 uint32 words (16 GiB)"),
+    "u16_2p20": (16, 1 << 20, I.Dist.uniform(), "pospopcnt16, 2^20 uint16 words (2 MiB)"),
 }
-DEFAULT_WORKLOAD = "u16-2^33"
+DEFAULT_WORKLOAD = "u16_2p33"
 
 
 def kernel_source_hash() -> str:
@@ -61,7 +61,7 @@ def kernel_source_hash() -> str:
 def read_traffic(kernel_tag: str, workload: str, src_hash: str, per_launch_algo_bytes: int):
     """HBM bytes per launch from the committed PMC summary of this kernel and
     workload, if the summary was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel_tag}_{workload.replace('^', '')}.txt")
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel_tag}_{workload}.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -135,6 +135,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceiling", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-reference", type=int, default=0, metavar="BYTES",
+                    help="only run --steps device-to-device copies of BYTES bytes (a plain copy "
+                         "kernel of known traffic, to scale profiler byte counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -145,6 +148,17 @@ def main():
 
     import torch
     from paper_1911_02696_amd import api
+
+    if args.copy_reference:
+        src = torch.ones(args.copy_reference, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes": args.copy_reference, "copies": args.steps,
+                          "read_bytes_per_copy": args.copy_reference,
+                          "write_bytes_per_copy": args.copy_reference}))
+        return
 
     k, n, dist, desc = WORKLOADS[args.workload]
     nbytes = n * (k // 8)

@@ -19,6 +19,9 @@ namespace ppc {
 
 constexpr int kWave = 64;
 
+// Four dwords, as one 16-byte load.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // Carry-save adder (Sec. 2): l = a xor b xor c, h = majority(a, b, c).  gfx950's
 // three-input bitwise op takes the truth table as an 8-bit immediate, the same
 // encoding Sec. 3 derives for the AVX-512 ternary-logic instruction (Table 2:
