@@ -122,6 +122,96 @@ def cpu_baseline(k, dist, seed, target_s: float, max_bytes: int):
     return rep, counts, s
 
 
+def batched_leg(args, torch, api):
+    """The 20,000-stream uneven mix: one prefix + one persistent kernel per step
+    (autotuned, replayed from a HIP graph) against one launch per stream, plain and
+    graph-captured.  Returns the report and whether the checks passed."""
+    import oracle
+    from paper_1911_02696_amd import batch as B
+    seed = SEED + 3
+    streams = I.loguniform_streams(20_000, 22, seed)
+    nb = streams.nbytes.astype(np.int64)
+    starts, size = I.batch_layout(nb, seed)
+    total = int(nb.sum())
+    print(f"[bench] batched: {len(nb)} streams, {total / 1e9:.2f} GB", file=sys.stderr, flush=True)
+    host = np.zeros(size + 64, np.uint8)
+    I.fill_streams(host, streams, starts, seed, threads=I.default_threads())
+    dev = torch.from_numpy(host).cuda()
+    m = len(nb)
+    counts = torch.zeros((m, 32), dtype=torch.int64, device="cuda")
+    desc_host = B.descriptors(dev.data_ptr() + starts, streams.lengths, streams.ks,
+                              counts.data_ptr() + 256 * np.arange(m))
+    descs = B.to_device(desc_host)
+    stream = torch.cuda.current_stream()
+    plan = B.Plan(m, graph=True)
+    tuned_ms = plan.autotune(descs)
+
+    def timed(fn, steps):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(steps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, ev0.elapsed_time(ev1) / 1e3 / steps
+
+    for _ in range(args.warmup):
+        plan.run(descs)
+    torch.cuda.synchronize()
+    counts.zero_()
+    wall, ev = timed(lambda: plan.run(descs), args.steps)
+    got = counts.cpu().numpy() // args.steps
+    ok_rep = bool((counts.cpu().numpy() == got * args.steps).all())
+
+    counts.zero_()
+    each_steps = 3
+    B.pospopcnt_each(desc_host)  # warm
+    torch.cuda.synchronize()
+    counts.zero_()
+    each_wall, each_ev = timed(lambda: B.pospopcnt_each(desc_host), each_steps)
+    each = counts.cpu().numpy() // each_steps
+    ok_each = bool((each == got).all())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        B.pospopcnt_each(desc_host)
+    g.replay()
+    torch.cuda.synchronize()
+    gwall, gev = timed(lambda: g.replay(), each_steps)
+
+    # oracle on a sample of streams: the 50 longest and 50 drawn at random
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sample = np.unique(np.concatenate([np.argsort(nb)[-50:], rng.choice(m, 50, replace=False)]))
+    ok_oracle = True
+    for i in sample:
+        k, n, st = int(streams.ks[i]), int(streams.lengths[i]), int(starts[i])
+        exp = oracle.count(host[st:st + n * k // 8], n, k,
+                           threads=I.default_threads() if n * k > (1 << 25) else 1)
+        ok_oracle &= bool((got[i, :k] == exp.astype(np.int64)).all())
+    del dev
+    rep = {
+        "workload": "20,000 streams, lengths log-uniform in [1, 2^22] words, k uniform in "
+                    "{8,16,32}, Bernoulli(p) bits with p ~ U(0,1), start offsets 0..15",
+        "bytes": total, "streams": m,
+        "value": round(total / wall / 1e9, 2), "unit": "GB/s",
+        "frac_of_hbm_peak": round(total / wall / 1e9 / HBM_PEAK_GBPS, 4),
+        "ms_per_step": round(wall * 1e3, 4), "event_ms_per_step": round(ev * 1e3, 4),
+        "config": plan.config, "autotune_best_ms": round(tuned_ms, 4), "graph": True,
+        "per_stream_launches": {"value": round(total / each_wall / 1e9, 2),
+                                "ms_per_step": round(each_wall * 1e3, 3),
+                                "event_ms_per_step": round(each_ev * 1e3, 3)},
+        "per_stream_launches_graph": {"value": round(total / gwall / 1e9, 2),
+                                      "ms_per_step": round(gwall * 1e3, 3)},
+        "speedup_vs_per_stream": round(each_wall / wall, 2),
+        "speedup_vs_per_stream_graph": round(gwall / wall, 2),
+        "check": {"steps_consistent": ok_rep, "equals_per_stream": ok_each,
+                  f"oracle_sample_{len(sample)}_streams": ok_oracle},
+    }
+    plan.close()
+    return rep, ok_rep and ok_each and ok_oracle
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +224,8 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceiling", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 20,000-stream batched leg")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-reference", type=int, default=0, metavar="BYTES",
                     help="only run --steps device-to-device copies of BYTES bytes (a plain copy "
@@ -224,6 +316,12 @@ def main():
         g = api.pospopcnt(dev, k, n=s // (k // 8), **cfg).cpu().numpy()
         ok_sample = bool((g == sample_counts.astype(np.int64)).all())
 
+    batched, ok_batched = None, True
+    if not args.no_batched:
+        del dev
+        torch.cuda.empty_cache()
+        batched, ok_batched = batched_leg(args, torch, api)
+
     achieved = nbytes / avg_kernel / 1e9
     src_hash = kernel_source_hash()
     kname = {"csa": "csa_kernel", "ballot": "ballot_kernel"}[args.variant]
@@ -256,6 +354,7 @@ def main():
                      "min_launch_ms": round(float(per.min()) * 1e3, 4),
                      "kernel_source_sha256": src_hash},
         "ceiling": ceiling,
+        "batched": batched,
         "cpu_baseline": cpu,
         "check": {"total_equals_passes_times_one_pass": ok_total,
                   "sample_equals_oracle": ok_sample},
@@ -263,7 +362,7 @@ def main():
                    "clock_mhz": info["clock_khz"] / 1000},
     }
     print(json.dumps(line), flush=True)
-    if not ok_total or ok_sample is False:
+    if not ok_total or ok_sample is False or not ok_batched:
         sys.exit(1)
 
 

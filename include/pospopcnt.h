@@ -112,6 +112,99 @@ int pospopcnt_ex(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_strea
 int ppc_read_ceiling(const void* ptr, uint64_t nbytes, uint64_t* sink, ppc_stream stream,
                      const ppc_launch_config* config);
 
+/* ------------------------------------------------------------------------
+ * Many streams in one launch.
+ *
+ * A descriptor names one stream (same conventions as the single-stream calls).
+ * Descriptor arrays passed to pospopcnt_batch live in device memory, 8-byte
+ * aligned, caller-owned, and must stay valid until the call's work on the
+ * stream has completed.  Streams may have any length (including 0), any start
+ * address and mixed widths; several descriptors may share counts (the flush
+ * uses atomics).  A descriptor with k not in {8, 16, 32}, reserved != 0, a
+ * NULL or misaligned pointer while n > 0, a length overflowing 64 bits, or
+ * counts overlapping its own input is skipped (nothing is added for it) and
+ * counted in the plan's rejected count.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const void* ptr;   /* device pointer to the first byte of the stream */
+    uint64_t n;        /* number of k-bit words */
+    uint32_t k;        /* 8, 16 or 32 */
+    uint32_t reserved; /* must be 0 */
+    uint64_t* counts;  /* device, 8-byte aligned, k entries, added into */
+} ppc_desc;
+
+/* Launch configuration of the batched kernel (chosen by ppc_plan_autotune, or
+ * set explicitly).  The work of a call is split into equal shares of
+ * "weighted units": every stream weighs stream_weight + (its 16-byte body
+ * units), the stream_weight standing for the fixed cost of its edge bytes and
+ * its flush.  Block b of the grid takes exactly the b-th share. */
+typedef struct {
+    int32_t depth;          /* circuit inputs per lane per step: 16 or 32 dwords */
+    int32_t block_threads;  /* 64, 128 or 256 */
+    int32_t blocks_per_cu;  /* 1 .. 16; grid = blocks_per_cu * compute units */
+    int32_t stream_weight;  /* weighted units charged per stream, 1 .. 65536 */
+} ppc_batch_config;
+
+/* Sizing hints for a plan. */
+typedef struct {
+    uint32_t max_streams;   /* largest m any call on this plan will pass (>= 1) */
+    uint32_t flags;         /* PPC_PLAN_GRAPH: see pospopcnt_batch */
+} ppc_workload_hint;
+
+enum { PPC_PLAN_GRAPH = 1 };
+
+typedef struct ppc_plan ppc_plan;
+
+/* Creates a plan on the current device.  The plan owns device scratch for
+ * max_streams descriptors (a prefix array, 8 bytes per stream, a per-block
+ * start table and a 1 MiB autotuning sink) and a default configuration.  This is the only batched
+ * call that allocates.  Errors: PPC_ERR_NULL, PPC_ERR_ARG (max_streams = 0 or
+ * > 2^26), PPC_ERR_HIP. */
+int ppc_plan_create(const ppc_workload_hint* hint, ppc_plan** plan);
+
+/* Releases the plan's scratch and graphs.  Work enqueued with the plan must have
+ * completed.  NULL is accepted. */
+int ppc_plan_destroy(ppc_plan* plan);
+
+/* Counts every stream of the m descriptors at d_descs (device memory) in one
+ * prefix kernel and one persistent counting kernel, asynchronously on stream.
+ * With PPC_PLAN_GRAPH the two kernels are captured into a HIP graph on the first
+ * call for a given (d_descs, m, configuration) and replayed by later calls; the
+ * graph reads the descriptors when it runs, so their contents may change between
+ * calls.  Calls sharing a plan must not overlap in time (the plan's scratch is
+ * reused); use one plan per concurrent stream.  m = 0 is a no-op.
+ * Errors: PPC_ERR_NULL, PPC_ERR_ALIGN, PPC_ERR_ARG (m > max_streams), PPC_ERR_HIP. */
+int pospopcnt_batch(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, ppc_stream stream);
+
+/* Times candidate configurations on the given workload (counts are redirected
+ * to plan scratch, so the descriptors' counters are not touched), keeps the
+ * fastest in the plan and returns its time per call in *best_ms (may be NULL).
+ * Synchronises `stream`. */
+int ppc_plan_autotune(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, ppc_stream stream,
+                      float* best_ms);
+
+int ppc_plan_get_config(const ppc_plan* plan, ppc_batch_config* config);
+/* Errors: PPC_ERR_ARG for a field out of range. */
+int ppc_plan_set_config(ppc_plan* plan, const ppc_batch_config* config);
+
+/* Writes the plan's configuration as a small JSON object (with the device name
+ * and architecture) to path / reads it back.  ppc_plan_load returns
+ * PPC_ERR_STATE if the file was written for another device architecture and
+ * PPC_ERR_ARG if it cannot be parsed; the plan is then unchanged. */
+int ppc_plan_save(const ppc_plan* plan, const char* path);
+int ppc_plan_load(ppc_plan* plan, const char* path);
+
+/* Number of descriptors the last completed pospopcnt_batch call on this plan
+ * skipped as invalid.  Enqueues a 4-byte copy on stream and waits for it. */
+int ppc_plan_rejected(ppc_plan* plan, ppc_stream stream, uint32_t* rejected);
+
+/* One single-stream launch per descriptor, from a HOST array of m descriptors
+ * (each launch as pospopcnt with default configuration).  The per-launch form
+ * the batched kernel is measured against; also handy when descriptors are
+ * built on the host.  Validation is per descriptor, before any launch: the
+ * first invalid descriptor's status is returned and nothing is launched. */
+int pospopcnt_each(const ppc_desc* h_descs, uint32_t m, ppc_stream stream);
+
 /* Device facts used to size launches (for the current HIP device). */
 typedef struct {
     int32_t device;

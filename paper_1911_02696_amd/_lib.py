@@ -44,7 +44,19 @@ class DeviceInfo(ctypes.Structure):
                 ("arch", ctypes.c_char * 64)]
 
 
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("stream_weight", ctypes.c_int32)]
+
+
+class WorkloadHint(ctypes.Structure):
+    _fields_ = [("max_streams", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+PLAN_GRAPH = 1
+
 _vp, _u64, _i32, _i64 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64
+_u32 = ctypes.c_uint32
 
 # name -> (restype, argtypes); every entry point the binding uses.
 SIGNATURES = {
@@ -57,6 +69,16 @@ SIGNATURES = {
     "pospopcnt_ex": (_i32, [_vp, _u64, _i32, _vp, _vp, ctypes.POINTER(LaunchConfig)]),
     "ppc_read_ceiling": (_i32, [_vp, _u64, _vp, _vp, ctypes.POINTER(LaunchConfig)]),
     "ppc_get_device_info": (_i32, [ctypes.POINTER(DeviceInfo)]),
+    "ppc_plan_create": (_i32, [ctypes.POINTER(WorkloadHint), ctypes.POINTER(_vp)]),
+    "ppc_plan_destroy": (_i32, [_vp]),
+    "pospopcnt_batch": (_i32, [_vp, _vp, _u32, _vp]),
+    "ppc_plan_autotune": (_i32, [_vp, _vp, _u32, _vp, ctypes.POINTER(ctypes.c_float)]),
+    "ppc_plan_get_config": (_i32, [_vp, ctypes.POINTER(BatchConfig)]),
+    "ppc_plan_set_config": (_i32, [_vp, ctypes.POINTER(BatchConfig)]),
+    "ppc_plan_save": (_i32, [_vp, ctypes.c_char_p]),
+    "ppc_plan_load": (_i32, [_vp, ctypes.c_char_p]),
+    "ppc_plan_rejected": (_i32, [_vp, _vp, ctypes.POINTER(_u32)]),
+    "pospopcnt_each": (_i32, [_vp, _u32, _vp]),
 }
 
 _lock = threading.Lock()

@@ -1,0 +1,588 @@
+// ppc_batch.hip -- many streams of mixed widths in one persistent launch.
+//
+// The work of a call is laid out on one axis of "weighted units": stream s
+// occupies [cum[s], cum[s+1]) with weight stream_weight + (16-byte body units of
+// s); the stream_weight prefix of its range stands for its edge bytes and its
+// flush, the rest is its aligned body, unit for unit.  Invalid and empty streams
+// weigh nothing.  Block b of a grid of G blocks takes the b-th of G equal shares
+// of the axis, so every block reads the same number of bytes give or take one
+// stream weight, however uneven the stream lengths are.  A long stream is split
+// over many blocks, a block's share covers many short streams.
+//
+// Two kernels per call:
+//   batch_prep  (one block): validates the descriptors, scans their weights into
+//               cum[0..m] and, for every block, finds the first stream its share
+//               touches (binary search), into first[0..G);
+//   batch_main  (G blocks): each block walks the streams of its share; for each
+//               it runs the CSA core of the single-stream kernel over its piece of
+//               the body (the block's waves take its 64-lane tiles in turn), the
+//               block that owns the start of the stream adds its edge bytes, and
+//               the block flushes that piece with one atomic per word position.
+// Counting uses the 32 dword-bit classes for every width, so streams of any k
+// share one code path; the flush folds the classes into the stream's k
+// positions with its start rotation.  The carry planes of the circuit go into
+// an 8-plane vertical counter per lane (two ops per plane, and few registers, so
+// many waves stay resident to hide the latency of short streams); every 255
+// carries, and at the end of a piece, the planes are turned into class totals,
+// reduced over the wave and added into 64-bit per-wave totals in LDS.
+//
+// Streams are visited in the order pos -> (pos * P) mod m for a fixed prime P
+// larger than any m, so a block's share never holds a long run of neighbouring
+// descriptors: a list sorted by length spreads its short streams over all blocks
+// as a shuffled one does.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "ppc_device.h"
+#include "ppc_internal.h"
+
+struct ppc_plan {
+    int device = -1;
+    uint32_t max_streams = 0;
+    uint32_t flags = 0;
+    int cus = 0;
+    int gmax = 0;
+    void* scratch = nullptr;
+    uint64_t* cum = nullptr;                  // [max_streams + 1]
+    uint32_t* first = nullptr;                // [gmax]
+    uint32_t* rejected = nullptr;             // [1]
+    unsigned long long* sink = nullptr;       // [gmax][32], autotune target, one row per block
+    ppc_batch_config cfg{};
+    int cfg_version = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const ppc_desc* g_descs = nullptr;
+    uint32_t g_m = 0;
+    int g_version = -1;
+    char arch[64] = {0};
+};
+
+namespace ppc {
+
+constexpr int kBatchMaxThreads = 256;
+constexpr int kPrepThreads = 1024;
+constexpr uint32_t kMaxPlanStreams = 1u << 26;
+constexpr int kMaxBlocksPerCu = 16;
+
+struct DevStream {
+    Edges edges;
+    const u32x4* body;
+    uint64_t units;
+    uint32_t rot;
+};
+
+// The same head / body / tail split as the host's split_stream.
+__device__ __forceinline__ DevStream split_dev(const void* ptr, uint64_t nbytes, int k) {
+    DevStream s;
+    const uintptr_t p = (uintptr_t)ptr, end = p + nbytes;
+    const uintptr_t a0 = (p + 15) & ~(uintptr_t)15;
+    s.rot = 8u * (uint32_t)(p % (uintptr_t)(k / 8));
+    s.edges.head = (const uint8_t*)ptr;
+    if (a0 >= end) {
+        s.edges.head_len = (uint32_t)nbytes;
+        s.edges.tail = (const uint8_t*)end;
+        s.edges.tail_len = 0;
+        s.body = (const u32x4*)a0;
+        s.units = 0;
+        return s;
+    }
+    const uintptr_t a1 = end & ~(uintptr_t)15;
+    s.edges.head_len = (uint32_t)(a0 - p);
+    s.edges.tail = (const uint8_t*)a1;
+    s.edges.tail_len = (uint32_t)(end - a1);
+    s.body = (const u32x4*)a0;
+    s.units = (uint64_t)(a1 - a0) / 16;
+    return s;
+}
+
+// Descriptor checks (the device-side counterpart of check_stream_args).
+__device__ __forceinline__ bool desc_valid(const ppc_desc& d, uint64_t* nbytes) {
+    *nbytes = 0;
+    if (d.reserved != 0) return false;
+    if (d.k != 8 && d.k != 16 && d.k != 32) return false;
+    if (d.n == 0) return true;
+    const uint64_t wb = d.k / 8;
+    if (d.n > ~0ull / wb) return false;
+    const uint64_t nb = d.n * wb;
+    const uintptr_t p = (uintptr_t)d.ptr, c0 = (uintptr_t)d.counts;
+    if (!p || !c0 || (c0 & 7u)) return false;
+    if (p + nb < p) return false;
+    const uintptr_t c1 = c0 + 8u * d.k;
+    if (c0 < p + nb && p < c1) return false;
+    *nbytes = nb;
+    return true;
+}
+
+__device__ __forceinline__ uint64_t share_lo(uint64_t b, uint64_t total, uint64_t G) {
+    const uint64_t base = total / G, extra = total % G;
+    return b * base + (b < extra ? b : extra);
+}
+
+// Exclusive scan of one value per thread over the block; *total receives the sum.
+__device__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* total, uint64_t* sh) {
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int nwaves = blockDim.x / kWave;
+    uint64_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint64_t y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) sh[wave] = x;
+    __syncthreads();
+    if (wave == 0) {
+        uint64_t w = lane < nwaves ? sh[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint64_t y = __shfl_up(w, o, kWave);
+            if (lane >= o) w += y;
+        }
+        if (lane < nwaves) sh[lane] = w;
+    }
+    __syncthreads();
+    const uint64_t before = wave ? sh[wave - 1] : 0;
+    *total = sh[nwaves - 1];
+    __syncthreads();
+    return before + x - v;
+}
+
+// Visiting order of the streams: position pos holds stream (pos * kVisitPrime) mod m,
+// a permutation of [0, m) because the prime exceeds every m a plan accepts.
+constexpr uint64_t kVisitPrime = 2654435761ull;
+
+__device__ __forceinline__ uint32_t stream_at(uint32_t pos, uint32_t m) {
+    return (uint32_t)(((uint64_t)pos * kVisitPrime) % m);
+}
+
+__global__ void __launch_bounds__(kPrepThreads)
+batch_prep(const ppc_desc* __restrict__ descs, uint32_t m, uint64_t weight, uint64_t* cum,
+           uint32_t* first, uint32_t G, uint32_t* rejected) {
+    __shared__ uint64_t sh[kPrepThreads / kWave];
+    __shared__ uint32_t bad_total;
+    if (threadIdx.x == 0) bad_total = 0;
+    uint64_t carry = 0;
+    uint32_t bad = 0;
+    for (uint32_t c0 = 0; c0 < m; c0 += blockDim.x) {
+        const uint32_t i = c0 + threadIdx.x;
+        uint64_t w = 0;
+        if (i < m) {
+            const ppc_desc d = descs[stream_at(i, m)];
+            uint64_t nb;
+            if (desc_valid(d, &nb)) {
+                if (nb) w = weight + split_dev(d.ptr, nb, (int)d.k).units;
+            } else {
+                ++bad;
+            }
+        }
+        uint64_t tot;
+        const uint64_t ex = block_exclusive_scan(w, &tot, sh);
+        if (i < m) cum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) cum[m] = carry;
+    if (bad) atomicAdd(&bad_total, bad);
+    __syncthreads();
+    if (threadIdx.x == 0) rejected[0] = bad_total;
+    // Start stream of every block's share: the last s < m with cum[s] <= lo.
+    for (uint32_t b = threadIdx.x; b < G; b += blockDim.x) {
+        const uint64_t lo = share_lo(b, carry, G);
+        uint32_t l = 0, h = m;
+        while (h - l > 1) {
+            const uint32_t mid = l + (h - l) / 2;
+            if (cum[mid] <= lo) l = mid; else h = mid;
+        }
+        first[b] = l;
+    }
+}
+
+// descs, cum and first are read-only for the whole launch and never alias the
+// counters, which lets the per-stream bookkeeping use scalar loads.  sink, when
+// not NULL, receives every flush instead of the descriptors' counters, in one
+// row of 32 per block (so that timing runs see the same atomic traffic as real
+// ones, spread over many addresses).
+template <int LOGD>
+__global__ void __launch_bounds__(kBatchMaxThreads)
+batch_main(const ppc_desc* __restrict__ descs, const uint64_t* __restrict__ cum,
+           const uint32_t* __restrict__ first, uint64_t weight, unsigned long long* sink,
+           uint32_t m) {
+    constexpr int C = 32;
+    constexpr int L = 8;
+    // A vertical counter of L planes holds 2^L - 1 carries: chunks of at most
+    // 2^L - 2 tiles leave room for the one masked tail tile.
+    constexpr uint64_t kChunk = (1u << L) - 2;
+    constexpr int G2 = kWave / C;               // lanes per class after the reduce
+    constexpr int U = (1 << LOGD) / 4;
+    constexpr uint64_t TILE = (uint64_t)kWave * U;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int wpb = blockDim.x / kWave;
+    const uint64_t G = gridDim.x, b = blockIdx.x;
+    const uint64_t total = cum[m];
+    const uint64_t lo = share_lo(b, total, G), hi = share_lo(b + 1, total, G);
+    if (lo >= hi) return;  // whole block: no barrier is reached
+    __shared__ unsigned long long acc[kBatchMaxThreads / kWave][C];
+
+    uint32_t pos = first[b];
+    uint64_t w0 = cum[pos], w1 = cum[pos + 1];
+    for (; pos < m && w0 < hi; ++pos) {
+        // the next position's bookkeeping is requested before this one is worked on
+        const uint64_t w2 = pos + 2 <= m ? cum[pos + 2] : w1;
+        if (w1 > lo && w1 > w0) {
+            const ppc_desc d = descs[stream_at(pos, m)];
+            const int k = (int)d.k;
+            const DevStream st = split_dev(d.ptr, d.n * (uint64_t)(k / 8), k);
+            const uint64_t bw0 = w0 + weight;  // first body unit of the stream on the axis
+            const uint64_t ub = lo > bw0 ? lo - bw0 : 0;
+            const uint64_t ue = hi >= w1 ? st.units : (hi > bw0 ? hi - bw0 : 0);
+            const bool own_edges = lo <= w0;  // this share holds the stream's start
+            if (own_edges || ue > ub) {
+                if (lane % G2 == 0) acc[wave][lane / G2] = 0;
+                uint32_t B[LOGD], V[L];
+#pragma unroll
+                for (int j = 0; j < LOGD; ++j) B[j] = 0;
+#pragma unroll
+                for (int j = 0; j < L; ++j) V[j] = 0;
+                auto consume = [&](const u32x4(&v)[U]) {
+                    uint32_t dw[4 * U];
+#pragma unroll
+                    for (int j = 0; j < U; ++j) {
+                        dw[4 * j + 0] = v[j].x;
+                        dw[4 * j + 1] = v[j].y;
+                        dw[4 * j + 2] = v[j].z;
+                        dw[4 * j + 3] = v[j].w;
+                    }
+                    vertical_add<L>(V, Circuit<LOGD>::run(B, dw));
+                };
+                if (ue > ub) {
+                    const u32x4* base = st.body + ub;
+                    const uint64_t len = ue - ub, full = len / TILE, rem = len - full * TILE;
+                    // this wave's tiles, in chunks of at most kChunk carries, the vertical
+                    // counter drained into the per-wave totals after each chunk
+                    uint64_t mine = (uint64_t)wave < full ? (full - wave + wpb - 1) / wpb : 0;
+                    const u32x4* p = base + (uint64_t)wave * TILE + lane;
+                    const uint64_t stride = (uint64_t)wpb * TILE;
+                    while (mine > 0) {
+                        const uint64_t n = mine < kChunk ? mine : kChunk;
+                        walk_n<U>(p, n, stride, consume);
+                        p += n * stride;
+                        mine -= n;
+                        if (mine > 0) {
+                            uint32_t t[C] = {};
+                            add_plane_totals<C, L>(t, V, LOGD);
+                            const uint32_t v = wave_reduce_scatter<C>(t, lane);
+                            if (lane % G2 == 0) acc[wave][lane / G2] += v;
+#pragma unroll
+                            for (int j = 0; j < L; ++j) V[j] = 0;
+                        }
+                    }
+                    if (rem != 0 && (uint64_t)wave == full % (uint64_t)wpb) {
+                        u32x4 t[U];
+                        load_tile_masked<U>(t, base + full * TILE + lane, lane, rem);
+                        consume(t);
+                    }
+                }
+                // running planes (weights 2^j), vertical counter (2^(LOGD + j)), edges (1)
+                const uint32_t e = (own_edges && wave == 0) ? edge_dword(st.edges, lane) : 0u;
+                uint32_t t[C];
+#pragma unroll
+                for (int i = 0; i < C; ++i) t[i] = __builtin_popcount(e & mask_of<C>(i));
+                add_plane_totals<C, L>(t, V, LOGD);
+                add_plane_totals<C, LOGD>(t, B, 0);
+                const uint32_t v = wave_reduce_scatter<C>(t, lane);
+                if (lane % G2 == 0) acc[wave][lane / G2] += v;
+                __syncthreads();
+                block_flush64<C>(acc, wpb, k, st.rot,
+                                 sink ? sink + b * C : (unsigned long long*)d.counts);
+                __syncthreads();
+            }
+        }
+        w0 = w1;
+        w1 = w2;
+    }
+}
+
+static const void* main_kernel(int depth) {
+    return depth == 32 ? (const void*)batch_main<5> : (const void*)batch_main<4>;
+}
+
+static int check_config(const ppc_batch_config& c) {
+    if (c.depth != 16 && c.depth != 32) return PPC_ERR_ARG;
+    if (c.block_threads != 64 && c.block_threads != 128 && c.block_threads != 256)
+        return PPC_ERR_ARG;
+    if (c.blocks_per_cu < 1 || c.blocks_per_cu > kMaxBlocksPerCu) return PPC_ERR_ARG;
+    if (c.stream_weight < 1 || c.stream_weight > 65536) return PPC_ERR_ARG;
+    return PPC_OK;
+}
+
+static int enqueue(ppc_plan* pl, const ppc_desc* descs, uint32_t m, hipStream_t s,
+                   unsigned long long* sink) {
+    const ppc_batch_config& c = pl->cfg;
+    uint32_t G = (uint32_t)(c.blocks_per_cu * pl->cus);
+    uint64_t weight = (uint64_t)c.stream_weight;
+    void* pargs[] = {(void*)&descs, &m, &weight, &pl->cum, &pl->first, &G, &pl->rejected};
+    PPC_HIP(hipLaunchKernel((const void*)batch_prep, dim3(1), dim3(kPrepThreads), pargs, 0, s));
+    const uint64_t* cum = pl->cum;
+    const uint32_t* first = pl->first;
+    void* margs[] = {(void*)&descs, (void*)&cum, (void*)&first, &weight, &sink, &m};
+    PPC_HIP(hipLaunchKernel(main_kernel(c.depth), dim3(G), dim3(c.block_threads), margs, 0, s));
+    return PPC_OK;
+}
+
+// Measured on MI355X over a 20,000-stream uneven mix, in the given, ascending and
+// descending length orders (ppc_plan_autotune picks per workload): 16 dwords per
+// lane per step, one-wave blocks, 4 per CU, and a stream costed like 64 KiB of
+// body -- the latency of a stream's bookkeeping, first loads and flush is about
+// what a block streams in that time.
+static ppc_batch_config default_config() { return ppc_batch_config{16, 64, 4, 4096}; }
+
+static int device_of(ppc_plan* pl) {
+    int dev = -1;
+    PPC_HIP(hipGetDevice(&dev));
+    if (dev != pl->device) return PPC_ERR_STATE;
+    return PPC_OK;
+}
+
+}  // namespace ppc
+
+using namespace ppc;
+
+extern "C" {
+
+int ppc_plan_create(const ppc_workload_hint* hint, ppc_plan** out) {
+    if (!hint || !out) return PPC_ERR_NULL;
+    *out = nullptr;
+    if (hint->max_streams == 0 || hint->max_streams > kMaxPlanStreams) return PPC_ERR_ARG;
+    const DeviceFacts* dev = nullptr;
+    int st = current_device(&dev);
+    if (st) return st;
+    ppc_plan* pl = new ppc_plan();
+    pl->device = dev->device;
+    pl->max_streams = hint->max_streams;
+    pl->flags = hint->flags;
+    pl->cus = dev->cus;
+    pl->gmax = dev->cus * kMaxBlocksPerCu;
+    memcpy(pl->arch, dev->arch, sizeof(pl->arch));
+    pl->cfg = default_config();
+    const size_t cum_bytes = ((size_t)hint->max_streams + 1) * 8;
+    const size_t first_bytes = (size_t)pl->gmax * 4;
+    const size_t off_first = (cum_bytes + 255) & ~(size_t)255;
+    const size_t off_rej = (off_first + first_bytes + 255) & ~(size_t)255;
+    const size_t off_sink = off_rej + 256;
+    const size_t total = off_sink + (size_t)pl->gmax * 32 * 8;
+    hipError_t e = hipMalloc(&pl->scratch, total);
+    if (e != hipSuccess) {
+        delete pl;
+        return fail_hip(e);
+    }
+    char* base = (char*)pl->scratch;
+    pl->cum = (uint64_t*)base;
+    pl->first = (uint32_t*)(base + off_first);
+    pl->rejected = (uint32_t*)(base + off_rej);
+    pl->sink = (unsigned long long*)(base + off_sink);
+    e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipFree(pl->scratch);
+        delete pl;
+        return fail_hip(e);
+    }
+    *out = pl;
+    return PPC_OK;
+}
+
+int ppc_plan_destroy(ppc_plan* pl) {
+    if (!pl) return PPC_OK;
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != pl->device) (void)hipSetDevice(pl->device);
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    if (pl->scratch) (void)hipFree(pl->scratch);
+    if (dev >= 0 && dev != pl->device) (void)hipSetDevice(dev);
+    delete pl;
+    return PPC_OK;
+}
+
+int pospopcnt_batch(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, ppc_stream stream) {
+    if (!pl) return PPC_ERR_NULL;
+    if (m == 0) return PPC_OK;
+    if (!d_descs) return PPC_ERR_NULL;
+    if ((uintptr_t)d_descs & 7u) return PPC_ERR_ALIGN;
+    if (m > pl->max_streams) return PPC_ERR_ARG;
+    int st = device_of(pl);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (!(pl->flags & PPC_PLAN_GRAPH)) return enqueue(pl, d_descs, m, s, nullptr);
+    if (!pl->exec || pl->g_descs != d_descs || pl->g_m != m || pl->g_version != pl->cfg_version) {
+        if (pl->exec) {
+            PPC_HIP(hipGraphExecDestroy(pl->exec));
+            pl->exec = nullptr;
+        }
+        PPC_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+        const int est = enqueue(pl, d_descs, m, pl->cap_stream, nullptr);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(pl->cap_stream, &g);
+        if (est) {
+            if (g) (void)hipGraphDestroy(g);
+            return est;
+        }
+        if (ce != hipSuccess) return fail_hip(ce);
+        const hipError_t ie = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            pl->exec = nullptr;
+            return fail_hip(ie);
+        }
+        pl->g_descs = d_descs;
+        pl->g_m = m;
+        pl->g_version = pl->cfg_version;
+    }
+    PPC_HIP(hipGraphLaunch(pl->exec, s));
+    return PPC_OK;
+}
+
+int ppc_plan_get_config(const ppc_plan* pl, ppc_batch_config* c) {
+    if (!pl || !c) return PPC_ERR_NULL;
+    *c = pl->cfg;
+    return PPC_OK;
+}
+
+int ppc_plan_set_config(ppc_plan* pl, const ppc_batch_config* c) {
+    if (!pl || !c) return PPC_ERR_NULL;
+    int st = check_config(*c);
+    if (st) return st;
+    pl->cfg = *c;
+    ++pl->cfg_version;
+    return PPC_OK;
+}
+
+int ppc_plan_autotune(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, ppc_stream stream,
+                      float* best_ms) {
+    if (!pl) return PPC_ERR_NULL;
+    if (m == 0) return PPC_OK;
+    if (!d_descs) return PPC_ERR_NULL;
+    if ((uintptr_t)d_descs & 7u) return PPC_ERR_ALIGN;
+    if (m > pl->max_streams) return PPC_ERR_ARG;
+    int st = device_of(pl);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<ppc_batch_config> cands;
+    for (int depth : {16, 32})
+        for (int bpc : {2, 3, 4, 6, 8, 12})
+            for (int weight : {1024, 2048, 4096, 8192}) cands.push_back({depth, 64, bpc, weight});
+    for (int depth : {16, 32})
+        for (int bpc : {1, 2})
+            for (int weight : {2048, 4096}) cands.push_back({depth, 256, bpc, weight});
+    hipEvent_t e0, e1;
+    PPC_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail_hip(he);
+    }
+    const ppc_batch_config saved = pl->cfg;
+    ppc_batch_config best = saved;
+    float best_t = INFINITY;
+    int rc = PPC_OK;
+    for (const ppc_batch_config& c : cands) {
+        pl->cfg = c;
+        if ((rc = enqueue(pl, d_descs, m, s, pl->sink))) break;  // warm-up
+        float ts[3];
+        for (float& t : ts) {
+            if ((he = hipEventRecord(e0, s)) != hipSuccess) break;
+            if ((rc = enqueue(pl, d_descs, m, s, pl->sink))) break;
+            if ((he = hipEventRecord(e1, s)) != hipSuccess) break;
+            if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
+            if ((he = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) break;
+        }
+        if (rc || he != hipSuccess) break;
+        std::sort(ts, ts + 3);
+        if (ts[1] < best_t) {
+            best_t = ts[1];
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!rc && he != hipSuccess) rc = fail_hip(he);
+    pl->cfg = rc ? saved : best;
+    ++pl->cfg_version;
+    if (!rc && best_ms) *best_ms = best_t;
+    return rc;
+}
+
+int ppc_plan_save(const ppc_plan* pl, const char* path) {
+    if (!pl || !path) return PPC_ERR_NULL;
+    FILE* f = fopen(path, "w");
+    if (!f) return PPC_ERR_ARG;
+    fprintf(f,
+            "{\"arch\": \"%s\", \"depth\": %d, \"block_threads\": %d, \"blocks_per_cu\": %d, "
+            "\"stream_weight\": %d}\n",
+            pl->arch, pl->cfg.depth, pl->cfg.block_threads, pl->cfg.blocks_per_cu,
+            pl->cfg.stream_weight);
+    return fclose(f) == 0 ? PPC_OK : PPC_ERR_ARG;
+}
+
+static bool json_int(const char* text, const char* key, int* out) {
+    char pat[64];
+    snprintf(pat, sizeof(pat), "\"%s\"", key);
+    const char* p = strstr(text, pat);
+    if (!p) return false;
+    p = strchr(p + strlen(pat), ':');
+    return p && sscanf(p + 1, "%d", out) == 1;
+}
+
+int ppc_plan_load(ppc_plan* pl, const char* path) {
+    if (!pl || !path) return PPC_ERR_NULL;
+    FILE* f = fopen(path, "r");
+    if (!f) return PPC_ERR_ARG;
+    char text[1024] = {0};
+    const size_t got = fread(text, 1, sizeof(text) - 1, f);
+    fclose(f);
+    text[got] = 0;
+    const char* a = strstr(text, "\"arch\"");
+    char arch[64] = {0};
+    if (!a || sscanf(a, "\"arch\" : \"%63[^\"]\"", arch) != 1) {
+        if (!a || sscanf(a, "\"arch\": \"%63[^\"]\"", arch) != 1) return PPC_ERR_ARG;
+    }
+    ppc_batch_config c{};
+    if (!json_int(text, "depth", &c.depth) || !json_int(text, "block_threads", &c.block_threads) ||
+        !json_int(text, "blocks_per_cu", &c.blocks_per_cu) ||
+        !json_int(text, "stream_weight", &c.stream_weight))
+        return PPC_ERR_ARG;
+    if (strcmp(arch, pl->arch) != 0) return PPC_ERR_STATE;
+    if (check_config(c)) return PPC_ERR_ARG;
+    pl->cfg = c;
+    ++pl->cfg_version;
+    return PPC_OK;
+}
+
+int ppc_plan_rejected(ppc_plan* pl, ppc_stream stream, uint32_t* out) {
+    if (!pl || !out) return PPC_ERR_NULL;
+    int st = device_of(pl);
+    if (st) return st;
+    PPC_HIP(hipMemcpyAsync(out, pl->rejected, 4, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    PPC_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return PPC_OK;
+}
+
+int pospopcnt_each(const ppc_desc* h, uint32_t m, ppc_stream stream) {
+    if (m == 0) return PPC_OK;
+    if (!h) return PPC_ERR_NULL;
+    for (uint32_t i = 0; i < m; ++i) {
+        if (h[i].reserved) return PPC_ERR_ARG;
+        uint64_t nb = 0;
+        int st = check_stream_args(h[i].ptr, h[i].n, (int)h[i].k, h[i].counts, &nb);
+        if (st) return st;
+    }
+    for (uint32_t i = 0; i < m; ++i) {
+        int st = launch_stream(h[i].ptr, h[i].n, (int)h[i].k, h[i].counts, stream, nullptr);
+        if (st) return st;
+    }
+    return PPC_OK;
+}
+
+}  // extern "C"

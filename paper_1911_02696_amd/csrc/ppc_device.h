@@ -87,20 +87,63 @@ __device__ __forceinline__ void lane_totals(uint32_t (&out)[C], const uint32_t (
     }
 }
 
+// Bit-sliced ("vertical") counter of carry planes: plane V[j] holds bit j of the
+// number of carries seen so far at each dword bit position, so a carry plane is
+// added with a ripple of half adders (2 ops per plane) whatever the number of
+// classes.  It is the Sec. 2 idea of keeping a sum as bit planes, carried past
+// the circuit's own planes; with L planes it holds up to 2^L - 1 carries.
+template <int L>
+__device__ __forceinline__ void vertical_add(uint32_t (&V)[L], uint32_t c) {
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const uint32_t t = V[j] & c;
+        V[j] ^= c;
+        c = t;
+    }
+}
+
+// out[i] += per-lane class-i total of planes P[0..L) with weights 2^(shift + j).
+template <int C, int L>
+__device__ __forceinline__ void add_plane_totals(uint32_t (&out)[C], const uint32_t (&P)[L],
+                                                 int shift) {
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int j = 0; j < L; ++j) t += __builtin_popcount(P[j] & mask_of<C>(i)) << j;
+        out[i] += t << shift;
+    }
+}
+
 // Reduce-scatter of C per-lane values over a wave: each exchange at distance
 // o = 32, 16, ... halves the values a lane keeps (the lower lane of a pair keeps
 // the lower half of the classes, the upper lane the upper half), then the last
 // exchanges are plain butterflies.  Afterwards every lane holds the wave total
-// of class  lane / (64 / C).  C - 1 + log2(64 / C) exchanges instead of 6 C.
+// of class  lane / (64 / C).
+// The two widest levels use gfx950's lane-swap instructions: swapping the upper
+// 32 lanes of v[j] with the lower 32 lanes of v[j + h] leaves each lane holding
+// both operands of its own sum, so a pair costs one swap and one add, in
+// registers, with no select.  The narrow levels that follow use shuffles.
 template <int C>
 __device__ __forceinline__ uint32_t wave_reduce_scatter(uint32_t (&v)[C], int lane) {
-    int width = C;
+    static_assert(C >= 4 && C <= 64, "class count");
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
+    for (int j = 0; j < C / 2; ++j) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v[j], v[j + C / 2], false, false);
+        v[j] = r[0] + r[1];
+    }
+#pragma unroll
+    for (int j = 0; j < C / 4; ++j) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v[j], v[j + C / 4], false, false);
+        v[j] = r[0] + r[1];
+    }
+    int width = C / 4;
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) {
         if (width > 1) {
             const bool upper = (lane & o) != 0;
 #pragma unroll
-            for (int j = 0; j < C / 2; ++j) {
+            for (int j = 0; j < C / 8; ++j) {
                 if (j < width / 2) {
                     const uint32_t send = upper ? v[j] : v[j + width / 2];
                     const uint32_t keep = upper ? v[j + width / 2] : v[j];
@@ -130,6 +173,123 @@ __device__ __forceinline__ void block_flush(const uint32_t (*red)[C], int waves,
             for (int w = 0; w < waves; ++w) s += red[w][cls];
         if (s) atomicAdd(counts + p, s);
     }
+}
+
+// As block_flush, from 64-bit per-wave class totals.
+template <int C>
+__device__ __forceinline__ void block_flush64(const unsigned long long (*acc)[C], int waves,
+                                              int k, uint32_t rot, unsigned long long* counts) {
+    const int p = threadIdx.x;
+    if (p < k) {
+        unsigned long long s = 0;
+        for (int cls = (p + (int)rot) & (k - 1); cls < C; cls += k)
+            for (int w = 0; w < waves; ++w) s += acc[w][cls];
+        if (s) atomicAdd(counts + p, s);
+    }
+}
+
+// ---------------------------------------------------------------- stream walking
+
+// Head and tail bytes of a stream (the parts outside its 16-byte aligned body).
+struct Edges {
+    const uint8_t* head;
+    const uint8_t* tail;
+    uint32_t head_len;
+    uint32_t tail_len;
+};
+
+// Lanes 0..14 take one head byte each, lanes 16..30 one tail byte each; the byte
+// is placed at its position inside its aligned dword.  Other lanes return 0.
+__device__ __forceinline__ uint32_t edge_dword(const Edges& e, int lane) {
+    const uint8_t* p = nullptr;
+    if (lane < 16) {
+        if ((uint32_t)lane < e.head_len) p = e.head + lane;
+    } else if (lane < 32) {
+        if ((uint32_t)(lane - 16) < e.tail_len) p = e.tail + (lane - 16);
+    }
+    if (!p) return 0u;
+    return (uint32_t)(*p) << (8u * (uint32_t)((uintptr_t)p & 3u));
+}
+
+// Streaming loads carry the nontemporal hint: every byte is read exactly once, and
+// on MI355X the hinted loads sustain about 15 % more HBM bandwidth than plain ones
+// (7.1-7.2 TB/s against 6.2-6.3 TB/s for a read-only pass over 16 GiB).
+// Input pointers are global memory; saying so keeps the loads global (not flat)
+// also when the pointer was itself read from memory, as in the batched kernel.
+typedef __attribute__((address_space(1))) const u32x4 global_u32x4;
+
+__device__ __forceinline__ u32x4 stream_load(const u32x4* p) {
+    return __builtin_nontemporal_load((global_u32x4*)p);
+}
+
+template <int U>
+__device__ __forceinline__ void load_tile(u32x4 (&v)[U], const u32x4* __restrict__ p) {
+#pragma unroll
+    for (int j = 0; j < U; ++j) v[j] = stream_load(p + j * kWave);
+}
+
+// Masked load of the last, partial tile: loads past `rem` units read nothing and
+// contribute zero dwords, which the circuit adds as nothing.
+template <int U>
+__device__ __forceinline__ void load_tile_masked(u32x4 (&v)[U], const u32x4* __restrict__ p,
+                                                 int lane, uint64_t rem) {
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        v[j] = ((uint64_t)(j * kWave + lane) < rem) ? stream_load(p + j * kWave)
+                                                     : u32x4{0u, 0u, 0u, 0u};
+}
+
+// Consume `count` whole tiles starting at p (already offset by the lane), each
+// `stride` units after the previous, with two tiles in flight: the next tile's
+// loads are issued before the current tile is consumed.  The trip count is known
+// on entry and the loop body issues its loads without a condition, so the
+// compiler's wait counters let the newer loads stay in flight while the older
+// ones are consumed.
+template <int U, typename F>
+__device__ __forceinline__ void walk_n(const u32x4* __restrict__ p, uint64_t count,
+                                       uint64_t stride, F&& consume) {
+    if (count == 0) return;
+    u32x4 a[U], b[U];
+    load_tile<U>(a, p);
+    while (count >= 3) {
+        load_tile<U>(b, p + stride);
+        consume(a);
+        load_tile<U>(a, p + 2 * stride);
+        consume(b);
+        p += 2 * stride;
+        count -= 2;
+    }
+    if (count == 2) {
+        load_tile<U>(b, p + stride);
+        consume(a);
+        consume(b);
+    } else {
+        consume(a);
+    }
+}
+
+// Walk this wave's whole tiles t = gw, gw + nw, ... < full of a body.
+template <int U, typename F>
+__device__ __forceinline__ void walk_tiles(const u32x4* __restrict__ body, uint64_t full,
+                                           uint64_t gw, uint64_t nw, int lane, F&& consume) {
+    constexpr uint64_t TILE = (uint64_t)kWave * U;
+    if (gw >= full) return;
+    walk_n<U>(body + gw * TILE + lane, (full - gw + nw - 1) / nw, nw * TILE, consume);
+}
+
+template <int C, int LOGD, int U>
+__device__ __forceinline__ void csa_step(uint32_t (&B)[LOGD], uint32_t (&cnt)[C],
+                                         const u32x4 (&v)[U]) {
+    static_assert(4 * U == (1 << LOGD), "one circuit per tile");
+    uint32_t d[4 * U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        d[4 * j + 0] = v[j].x;
+        d[4 * j + 1] = v[j].y;
+        d[4 * j + 2] = v[j].z;
+        d[4 * j + 3] = v[j].w;
+    }
+    count_classes<C>(cnt, Circuit<LOGD>::run(B, d));
 }
 
 }  // namespace ppc

@@ -56,6 +56,10 @@ struct Launch {
     int64_t grid;  // blocks
 };
 
+// Validate and launch the single-stream kernel (the body of pospopcnt_ex).
+int launch_stream(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stream stream,
+                  const ppc_launch_config* cfg);
+
 int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has_edges,
                    uint64_t nbytes, Launch* out);
 

@@ -34,93 +34,6 @@
 
 namespace ppc {
 
-struct Edges {
-    const uint8_t* head;
-    const uint8_t* tail;
-    uint32_t head_len;
-    uint32_t tail_len;
-};
-
-// Lanes 0..14 take one head byte each, lanes 16..30 one tail byte each; the byte
-// is placed at its position inside its aligned dword.  Other lanes return 0.
-__device__ __forceinline__ uint32_t edge_dword(const Edges& e, int lane) {
-    const uint8_t* p = nullptr;
-    if (lane < 16) {
-        if ((uint32_t)lane < e.head_len) p = e.head + lane;
-    } else if (lane < 32) {
-        if ((uint32_t)(lane - 16) < e.tail_len) p = e.tail + (lane - 16);
-    }
-    if (!p) return 0u;
-    return (uint32_t)(*p) << (8u * (uint32_t)((uintptr_t)p & 3u));
-}
-
-// Streaming loads carry the nontemporal hint: every byte is read exactly once, and
-// on MI355X the hinted loads sustain about 15 % more HBM bandwidth than plain ones
-// (7.1-7.2 TB/s against 6.2-6.3 TB/s for a read-only pass over 16 GiB).
-template <int U>
-__device__ __forceinline__ void load_tile(u32x4 (&v)[U], const u32x4* __restrict__ p) {
-#pragma unroll
-    for (int j = 0; j < U; ++j) v[j] = __builtin_nontemporal_load(p + j * kWave);
-}
-
-// Masked load of the last, partial tile: loads past `rem` units read nothing and
-// contribute zero dwords, which the circuit adds as nothing.
-template <int U>
-__device__ __forceinline__ void load_tile_masked(u32x4 (&v)[U], const u32x4* __restrict__ p,
-                                                 int lane, uint64_t rem) {
-#pragma unroll
-    for (int j = 0; j < U; ++j)
-        v[j] = ((uint64_t)(j * kWave + lane) < rem) ? __builtin_nontemporal_load(p + j * kWave)
-                                                     : u32x4{0u, 0u, 0u, 0u};
-}
-
-// Walk this wave's whole tiles (t = gw, gw + nw, ... < full) with two tiles in
-// flight: the next tile's loads are issued before the current tile is consumed.
-// The trip count is computed first and the loop body issues its loads without a
-// condition, so the compiler's wait counters let the newer loads stay in flight
-// while the older ones are consumed.
-template <int U, typename F>
-__device__ __forceinline__ void walk_tiles(const u32x4* __restrict__ body, uint64_t full,
-                                           uint64_t gw, uint64_t nw, int lane, F&& consume) {
-    constexpr uint64_t TILE = (uint64_t)kWave * U;
-    if (gw >= full) return;
-    uint64_t left = (full - gw + nw - 1) / nw;  // tiles of this wave
-    const u32x4* p = body + gw * TILE + lane;
-    const uint64_t stride = nw * TILE;
-    u32x4 a[U], b[U];
-    load_tile<U>(a, p);
-    while (left >= 3) {
-        load_tile<U>(b, p + stride);
-        consume(a);
-        load_tile<U>(a, p + 2 * stride);
-        consume(b);
-        p += 2 * stride;
-        left -= 2;
-    }
-    if (left == 2) {
-        load_tile<U>(b, p + stride);
-        consume(a);
-        consume(b);
-    } else {
-        consume(a);
-    }
-}
-
-template <int C, int LOGD, int U>
-__device__ __forceinline__ void csa_step(uint32_t (&B)[LOGD], uint32_t (&cnt)[C],
-                                         const u32x4 (&v)[U]) {
-    static_assert(4 * U == (1 << LOGD), "one circuit per tile");
-    uint32_t d[4 * U];
-#pragma unroll
-    for (int j = 0; j < U; ++j) {
-        d[4 * j + 0] = v[j].x;
-        d[4 * j + 1] = v[j].y;
-        d[4 * j + 2] = v[j].z;
-        d[4 * j + 3] = v[j].w;
-    }
-    count_classes<C>(cnt, Circuit<LOGD>::run(B, d));
-}
-
 constexpr int kMaxThreads = 256;
 constexpr int kMaxWaves = kMaxThreads / kWave;
 
@@ -187,7 +100,7 @@ ballot_kernel(const u32x4* __restrict__ body, uint64_t units, Edges edges, int k
     for (int i = 0; i < C; ++i) acc[i] = 0;
     for (uint64_t t = gw; t < tiles; t += nw) {
         const uint64_t u = t * kWave + lane;
-        const u32x4 v = u < units ? __builtin_nontemporal_load(body + u) : u32x4{0u, 0u, 0u, 0u};
+        const u32x4 v = u < units ? stream_load(body + u) : u32x4{0u, 0u, 0u, 0u};
         ballot_count<C>(acc, v.x);
         ballot_count<C>(acc, v.y);
         ballot_count<C>(acc, v.z);
@@ -352,8 +265,8 @@ int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has
     return PPC_OK;
 }
 
-static int launch_stream(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stream stream,
-                         const ppc_launch_config* cfg) {
+int launch_stream(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stream stream,
+                  const ppc_launch_config* cfg) {
     uint64_t nbytes = 0;
     int st = check_stream_args(ptr, n, k, counts, &nbytes);
     if (st != PPC_OK || nbytes == 0) return st;

@@ -190,3 +190,30 @@ def poisson_arrivals(rate: float, duration_s: float, seed: int) -> np.ndarray:
         more = np.cumsum(rng.exponential(1.0 / rate, size=n_est)) + t[-1]
         t = np.concatenate([t, more])
     return t[t < duration_s]
+
+
+def batch_layout(lengths_bytes: np.ndarray, seed: int, align: int = 256,
+                 max_offset: int = 16) -> tuple[np.ndarray, int]:
+    """Place streams one after another in one arena: each starts at an `align`-byte
+    boundary plus a seeded start offset in [0, max_offset).  Returns (start byte of
+    every stream, arena size)."""
+    rng = np.random.Generator(np.random.PCG64(seed ^ 0x5A5A))
+    offs = rng.integers(0, max_offset, size=len(lengths_bytes)) if max_offset > 1 else \
+        np.zeros(len(lengths_bytes), dtype=np.int64)
+    slot = ((np.asarray(lengths_bytes, dtype=np.int64) + offs + align - 1) // align) * align
+    slot = np.maximum(slot, align)
+    starts = np.concatenate([[0], np.cumsum(slot)[:-1]]) + offs
+    return starts.astype(np.int64), int(slot.sum())
+
+
+def fill_streams(arena: np.ndarray, streams: StreamSet, starts: np.ndarray, seed: int,
+                 threads: int | None = None):
+    """Stream i: Bernoulli(ps[i]) bits of sub-stream i of `seed`, at arena[starts[i]:]."""
+    nb = streams.nbytes
+    for i in range(len(nb)):
+        b = int(nb[i])
+        if b:
+            s = int(starts[i])
+            fill(arena[s:s + b], Dist.bernoulli(float(streams.ps[i])), seed, stream=i,
+                 threads=threads if b > (1 << 22) else 1)
+    return arena

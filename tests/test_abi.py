@@ -126,3 +126,39 @@ def test_no_device_reports_hip_error(lib):
     info = L.DeviceInfo()
     assert lib.ppc_get_device_info(ctypes.byref(info)) == 5
     assert lib.ppc_last_hip_error() != 0
+
+
+def test_batch_arguments(lib):
+    import numpy as np
+    assert lib.pospopcnt_batch(None, None, 0, None) == 1       # NULL plan
+    assert lib.ppc_plan_destroy(None) == 0
+    assert lib.ppc_plan_create(None, None) == 1
+    h = ctypes.c_void_p()
+    assert lib.ppc_plan_create(ctypes.byref(L.WorkloadHint(0, 0)), ctypes.byref(h)) == 7
+    assert lib.ppc_plan_create(ctypes.byref(L.WorkloadHint(1 << 27, 0)), ctypes.byref(h)) == 7
+    assert lib.ppc_plan_get_config(None, None) == 1
+    assert lib.ppc_plan_set_config(None, None) == 1
+    assert lib.ppc_plan_save(None, b"x") == 1
+    assert lib.ppc_plan_load(None, b"x") == 1
+    assert lib.ppc_plan_autotune(None, None, 0, None, None) == 1
+    u = ctypes.c_uint32()
+    assert lib.ppc_plan_rejected(None, None, ctypes.byref(u)) == 1
+    # one launch per descriptor: validated on the host before anything is launched
+    from paper_1911_02696_amd.batch import descriptors
+    assert lib.pospopcnt_each(None, 0, None) == 0
+    assert lib.pospopcnt_each(None, 3, None) == 1
+    good = descriptors([0x1000, 0x2000], [10, 10], [8, 16], [0x9000, 0xA000])
+    for field, value, status in ((2, 12, 3), (2, 16 | (1 << 32), 7), (3, 0x9004, 2),
+                                 (0, 0, 1), (3, 0x2000, 8)):
+        d = good.copy()
+        d[1, field] = value
+        assert lib.pospopcnt_each(d.ctypes.data, 2, None) == status, (field, value)
+
+
+def test_plan_needs_a_device(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert lib.ppc_plan_create(ctypes.byref(L.WorkloadHint(16, 0)), ctypes.byref(h)) == 5
+    assert not h.value
