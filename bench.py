@@ -212,6 +212,70 @@ def batched_leg(args, torch, api):
     return rep, ok_rep and ok_each and ok_oracle
 
 
+def serving_leg(args, torch, api):
+    """Poisson arrivals at 50,000 requests/s for args.serve_seconds through the
+    continuous-batching server (64 GiB arena, inputs copied into it from
+    device-resident pools), then a shorter run counting in place."""
+    import oracle
+    from paper_1911_02696_amd import serve as S
+    seed = SEED + 4
+    pool_bytes = 1 << 29
+    trace = I.serving_trace(50_000, args.serve_seconds, seed, pool_bytes=pool_bytes)
+    print(f"[bench] serving: {len(trace.arrival)} requests over {args.serve_seconds} s, "
+          f"{trace.nbytes.sum() / 1e12:.2f} TB", file=sys.stderr, flush=True)
+    pools = S.Pools(trace, pool_bytes, seed)
+    reqs = pools.requests(trace)
+    report = {"workload": "Poisson arrivals 50,000 req/s, lengths log-uniform in [2^10, 2^26] "
+                          "words, k uniform in {8,16,32}, one-hot Zipf(1.1) or Bernoulli(0.5) "
+                          "inputs from device-resident pools", "arena_bytes": 64 << 30,
+              "max_requests": 4096, "max_batch": 1024, "streams": 4}
+    ok = True
+    for mode, seconds in (("copy", args.serve_seconds), ("in_place", min(3.0, args.serve_seconds))):
+        r = reqs[trace.arrival < seconds]
+        srv = S.Server(64 << 30, max_requests=4096, max_batch=1024, streams=4,
+                       in_place=(mode == "in_place"))
+        warm = r[:2000].copy()
+        warm["arrival"] = np.linspace(0, 0.02, len(warm))
+        srv.run_trace(warm)
+        srv.close()
+        srv = S.Server(64 << 30, max_requests=4096, max_batch=1024, streams=4,
+                       in_place=(mode == "in_place"))
+        comps = srv.run_trace(r)
+        st = srv.stats()
+        srv.close()
+        good = comps["status"] == 0
+        span = float(comps["completed"].max() - comps["arrival"].min())
+        lat = S.latency_summary(comps)
+        # sample checks: oracle and the same request counted alone
+        rng = np.random.Generator(np.random.PCG64(seed))
+        sample = np.unique(np.concatenate([rng.choice(len(r), 100, replace=False),
+                                           np.argsort(trace.nbytes[:len(r)])[-20:]]))
+        ok_oracle = ok_alone = True
+        out = torch.zeros(32, dtype=torch.int64, device="cuda")
+        for i in sample:
+            k, n = int(trace.ks[i]), int(trace.lengths[i])
+            exp = oracle.count(pools.host_bytes(trace, i), n, k,
+                               threads=I.default_threads() if n * k > (1 << 25) else 1)
+            got = comps["counts"][i][:k]
+            ok_oracle &= bool((got == exp).all())
+            out.zero_()
+            api.pospopcnt_ptr(int(r[i]["src"]), n, k, out.data_ptr())
+            ok_alone &= bool((out.cpu().numpy()[:k] == got.astype(np.int64)).all())
+        ok &= bool(good.all()) and ok_oracle and ok_alone
+        report[mode] = dict(lat, seconds=seconds, gbps=round(st["bytes_counted"] / span / 1e9, 1),
+                            requests_per_s=round(len(r) / span, 1),
+                            launches=st["launches"], admitted=st["admitted"],
+                            rejected=st["rejected"], max_queued=st["max_queued"],
+                            max_inflight=st["max_inflight"],
+                            arena_peak_gib=round(st["arena_peak"] / 2**30, 3),
+                            check={"all_ok": bool(good.all()),
+                                   f"oracle_sample_{len(sample)}": ok_oracle,
+                                   "alone_equals_in_mix": ok_alone})
+    del pools
+    torch.cuda.empty_cache()
+    return report, ok
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +290,8 @@ def main():
     ap.add_argument("--no-ceiling", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 20,000-stream batched leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-reference", type=int, default=0, metavar="BYTES",
                     help="only run --steps device-to-device copies of BYTES bytes (a plain copy "
@@ -321,6 +387,10 @@ def main():
         del dev
         torch.cuda.empty_cache()
         batched, ok_batched = batched_leg(args, torch, api)
+        torch.cuda.empty_cache()
+    serving, ok_serving = None, True
+    if not args.no_serving:
+        serving, ok_serving = serving_leg(args, torch, api)
 
     achieved = nbytes / avg_kernel / 1e9
     src_hash = kernel_source_hash()
@@ -355,6 +425,7 @@ def main():
                      "kernel_source_sha256": src_hash},
         "ceiling": ceiling,
         "batched": batched,
+        "serving": serving,
         "cpu_baseline": cpu,
         "check": {"total_equals_passes_times_one_pass": ok_total,
                   "sample_equals_oracle": ok_sample},
@@ -362,7 +433,7 @@ def main():
                    "clock_mhz": info["clock_khz"] / 1000},
     }
     print(json.dumps(line), flush=True)
-    if not ok_total or ok_sample is False or not ok_batched:
+    if not ok_total or ok_sample is False or not ok_batched or not ok_serving:
         sys.exit(1)
 
 

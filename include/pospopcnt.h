@@ -205,6 +205,126 @@ int ppc_plan_rejected(ppc_plan* plan, ppc_stream stream, uint32_t* rejected);
  * first invalid descriptor's status is returned and nothing is launched. */
 int pospopcnt_each(const ppc_desc* h_descs, uint32_t m, ppc_stream stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ *
+ * Requests name a stream already in device memory (src, n, k).  The server
+ * admits them in arrival order while its memory budget and request slots allow:
+ * an admitted request gets a slab of its input size in the server's device
+ * arena, its bytes are copied there (unless PPC_SERVE_IN_PLACE), and it joins the
+ * next launch.  Each progress step reaps finished launches (their slabs and
+ * slots free up), admits waiting requests and launches every newly admitted one
+ * as one batched count on the next of the server's HIP streams, so launches
+ * overlap on the device while earlier ones still run.  Counts come back to the
+ * host with the launch and are reported per request with its timestamps.  The
+ * counting is the batched kernel's, so a request's counts are the same alone and
+ * in any mix.  A server is used from one host thread at a time.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    uint64_t arena_bytes;   /* device memory budget for admitted requests' inputs */
+    uint32_t max_requests;  /* requests admitted at once (1 .. 2^20) */
+    uint32_t max_batch;     /* requests per launch (1 .. 65536) */
+    uint32_t streams;       /* HIP streams launches rotate over (1 .. 8) */
+    uint32_t flags;         /* PPC_SERVE_IN_PLACE, PPC_SERVE_FIFO_BYPASS */
+} ppc_server_config;
+
+enum {
+    /* count at the request's own src (its slab is reserved for accounting only) */
+    PPC_SERVE_IN_PLACE = 1,
+    /* when the oldest waiting request does not fit, later ones that fit may pass it */
+    PPC_SERVE_FIFO_BYPASS = 2
+};
+
+typedef struct {
+    const void* src;    /* device pointer of the request's input, any alignment */
+    uint64_t n;         /* words */
+    uint32_t k;         /* 8, 16 or 32 */
+    uint32_t reserved;  /* must be 0 */
+    double arrival;     /* arrival time in seconds (server clock for ppc_server_submit,
+                           offset from the start of the replay for ppc_server_run_trace) */
+    uint64_t tag;       /* caller's identifier, returned with the completion */
+} ppc_request;
+
+typedef struct {
+    uint64_t tag;
+    int32_t status;     /* PPC_OK, PPC_ERR_BUDGET (larger than the arena), PPC_ERR_WIDTH,
+                           PPC_ERR_NULL, PPC_ERR_ARG, or PPC_ERR_HIP if its launch failed */
+    uint32_t batch;     /* requests in the launch that counted it */
+    double arrival, admitted, launched, completed;  /* server clock, seconds */
+    uint64_t counts[32];                            /* first k entries used */
+} ppc_completion;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, rejected, launches;
+    uint64_t queued_now, inflight_now, max_queued, max_inflight;
+    uint64_t arena_used_now, arena_peak, bytes_counted;
+} ppc_server_stats;
+
+/* Executor callbacks, for driving the scheduler with something other than the
+ * GPU (tests use the CPU oracle).  launch receives the admitted requests of one
+ * launch, each with the offset of its slab in a virtual arena; poll reports
+ * whether a launch has finished; results fills n x 32 counts in launch order;
+ * release forgets the launch.  Every callback returns a status (PPC_OK or an
+ * error, which fails the requests of that launch with that status). */
+typedef struct {
+    const void* src;
+    uint64_t n;
+    uint32_t k;
+    uint32_t reserved;
+    uint64_t arena_offset;
+    uint64_t tag;
+} ppc_exec_item;
+
+typedef struct {
+    int (*launch)(void* user, const ppc_exec_item* items, uint32_t n, uint64_t* handle);
+    int (*poll)(void* user, uint64_t handle, int* done);
+    int (*results)(void* user, uint64_t handle, uint64_t* counts);
+    int (*release)(void* user, uint64_t handle);
+} ppc_executor_ops;
+
+typedef struct ppc_server ppc_server;
+
+/* Creates a server on the current device: allocates the arena, the streams, one
+ * plan per stream and pinned staging for launches (the only serving call that
+ * allocates).  Errors: PPC_ERR_NULL, PPC_ERR_ARG, PPC_ERR_HIP. */
+int ppc_server_create(const ppc_server_config* config, ppc_server** server);
+
+/* Same scheduler over caller-supplied executor callbacks (no device memory is
+ * allocated; arena offsets are virtual).  ops and user must outlive the server. */
+int ppc_server_create_with_executor(const ppc_server_config* config,
+                                    const ppc_executor_ops* ops, void* user,
+                                    ppc_server** server);
+
+/* Waits for launches in flight, then releases everything.  NULL is accepted. */
+int ppc_server_destroy(ppc_server* server);
+
+/* Seconds since the server was created (steady clock). */
+double ppc_server_now(const ppc_server* server);
+
+/* Queues n requests (their arrival times are taken as given).  Requests that can
+ * never be served complete at once with an error status (larger than the arena:
+ * PPC_ERR_BUDGET).  Never blocks and never launches. */
+int ppc_server_submit(ppc_server* server, const ppc_request* requests, uint32_t n);
+
+/* One scheduling step: reap finished launches, admit, launch.  Optional outputs:
+ * requests launched and completed in this step. */
+int ppc_server_progress(ppc_server* server, uint32_t* launched, uint32_t* completed);
+
+/* Moves up to cap completions (oldest first) to out; *n_out receives how many. */
+int ppc_server_take_completions(ppc_server* server, ppc_completion* out, uint32_t cap,
+                                uint32_t* n_out);
+
+int ppc_server_get_stats(const ppc_server* server, ppc_server_stats* stats);
+
+/* Replays n requests in real time: request i is submitted when
+ * (now - start) >= requests[i].arrival (arrivals must be non-decreasing), and
+ * the server is progressed continuously until all n have completed.  out[i]
+ * receives request i's completion (out holds n entries); arrival times in out are
+ * on the server clock.  Returns PPC_OK when every request has completed, whatever
+ * their individual statuses. */
+int ppc_server_run_trace(ppc_server* server, const ppc_request* requests, uint32_t n,
+                         ppc_completion* out);
+
 /* Device facts used to size launches (for the current HIP device). */
 typedef struct {
     int32_t device;

@@ -1,0 +1,601 @@
+// ppc_serve.hip -- request loop with continuous batching over the batched count.
+//
+// Scheduler (host): requests wait in arrival order; a request is admitted when a
+// request slot is free and a slab of its input size fits in the device arena
+// (first fit, 256-byte granules).  Every progress step
+//   1. reaps finished launches: their completions are recorded with the counts
+//      and timestamps, their slabs and slots are released;
+//   2. admits waiting requests while slots and memory allow;
+//   3. launches the admitted requests not yet launched as one batch, if the
+//      executor has a launch slot free.
+// So requests that arrive while earlier launches run join the next launch, and
+// launches on different streams overlap on the device.
+//
+// GPU executor: a launch on stream s (launch slots rotate over the streams, two
+// per stream) enqueues, in order: the copy of every request's input from its
+// source into its slab (one kernel over 256 KiB chunks), the descriptor table,
+// zeroing of the launch's counts, the batched count (one plan per stream), the
+// copy of the counts to pinned host memory, and an event the scheduler polls.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
+#include <memory>
+#include <thread>
+#include <vector>
+
+#include "ppc_device.h"
+#include "ppc_internal.h"
+
+namespace ppc {
+
+constexpr uint64_t kGranule = 256;
+constexpr uint64_t kCopyChunk = 256 << 10;
+constexpr uint32_t kMaxServerRequests = 1u << 20;
+constexpr uint32_t kMaxServerBatch = 65536;
+constexpr double kStallSeconds = 120.0;  // run_trace gives up after this long without progress
+
+// ------------------------------------------------------------------ arena
+
+class Arena {
+  public:
+    explicit Arena(uint64_t size) : size_(size) {
+        if (size_) free_[0] = size_;
+    }
+    static uint64_t granules(uint64_t bytes) {
+        return ((bytes ? bytes : 1) + kGranule - 1) & ~(kGranule - 1);
+    }
+    bool alloc(uint64_t bytes, uint64_t* off) {
+        const uint64_t need = granules(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < need) continue;
+            *off = it->first;
+            const uint64_t rest = it->second - need, noff = it->first + need;
+            free_.erase(it);
+            if (rest) free_[noff] = rest;
+            used_ += need;
+            peak_ = std::max(peak_, used_);
+            return true;
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t bytes) {
+        uint64_t need = granules(bytes), start = off;
+        used_ -= need;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && next->first == off + need) {
+            need += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == start) {
+                start = prev->first;
+                need += prev->second;
+                free_.erase(prev);
+            }
+        }
+        free_[start] = need;
+    }
+    uint64_t used() const { return used_; }
+    uint64_t peak() const { return peak_; }
+    uint64_t size() const { return size_; }
+
+  private:
+    uint64_t size_, used_ = 0, peak_ = 0;
+    std::map<uint64_t, uint64_t> free_;  // offset -> length of free runs
+};
+
+// ------------------------------------------------------------------ executors
+
+struct Admitted {
+    ppc_request r;
+    uint64_t bytes, off;
+    double admitted;
+};
+
+class Executor {
+  public:
+    virtual ~Executor() = default;
+    virtual int launch(const std::vector<Admitted>& items, uint64_t* handle) = 0;
+    virtual int poll(uint64_t handle, bool* done) = 0;
+    virtual int results(uint64_t handle, uint64_t* counts) = 0;
+    virtual int release(uint64_t handle) = 0;
+    virtual size_t capacity() const = 0;  // launches in flight at most
+    virtual void wait_all() {}
+};
+
+class CallbackExecutor : public Executor {
+  public:
+    CallbackExecutor(const ppc_executor_ops& ops, void* user, size_t cap)
+        : ops_(ops), user_(user), cap_(cap) {}
+    int launch(const std::vector<Admitted>& items, uint64_t* handle) override {
+        std::vector<ppc_exec_item> v(items.size());
+        for (size_t i = 0; i < items.size(); ++i)
+            v[i] = {items[i].r.src, items[i].r.n, items[i].r.k, 0, items[i].off, items[i].r.tag};
+        return ops_.launch(user_, v.data(), (uint32_t)v.size(), handle);
+    }
+    int poll(uint64_t h, bool* done) override {
+        int d = 0;
+        const int st = ops_.poll(user_, h, &d);
+        *done = d != 0;
+        return st;
+    }
+    int results(uint64_t h, uint64_t* counts) override { return ops_.results(user_, h, counts); }
+    int release(uint64_t h) override { return ops_.release(user_, h); }
+    size_t capacity() const override { return cap_; }
+
+  private:
+    ppc_executor_ops ops_;
+    void* user_;
+    size_t cap_;
+};
+
+struct CopyChunk {
+    const uint8_t* src;
+    uint8_t* dst;
+    uint64_t bytes;
+};
+
+// Copies every chunk; a block takes chunks in turn.  16-byte units when source
+// and destination are both 16-byte aligned, bytes otherwise.
+__global__ void __launch_bounds__(256) copy_chunks(const CopyChunk* __restrict__ chunks,
+                                                   uint32_t n) {
+    for (uint32_t c = blockIdx.x; c < n; c += gridDim.x) {
+        const CopyChunk ch = chunks[c];
+        if ((((uintptr_t)ch.src | (uintptr_t)ch.dst) & 15u) == 0) {
+            const uint64_t units = ch.bytes / 16;
+            const u32x4* s = (const u32x4*)ch.src;
+            u32x4* d = (u32x4*)ch.dst;
+            for (uint64_t u = threadIdx.x; u < units; u += blockDim.x) d[u] = stream_load(s + u);
+            for (uint64_t b = units * 16 + threadIdx.x; b < ch.bytes; b += blockDim.x)
+                ch.dst[b] = ch.src[b];
+        } else {
+            for (uint64_t b = threadIdx.x; b < ch.bytes; b += blockDim.x) ch.dst[b] = ch.src[b];
+        }
+    }
+}
+
+class HipExecutor : public Executor {
+  public:
+    struct Slot {
+        int stream = 0;
+        bool busy = false;
+        uint32_t n = 0;
+        ppc_desc* d_descs = nullptr;
+        uint64_t* d_counts = nullptr;
+        CopyChunk* d_chunks = nullptr;
+        ppc_desc* h_descs = nullptr;
+        uint64_t* h_counts = nullptr;
+        CopyChunk* h_chunks = nullptr;
+        hipEvent_t done = nullptr;
+    };
+
+    int init(const ppc_server_config& c) {
+        cfg_ = c;
+        const DeviceFacts* dev = nullptr;
+        int st = current_device(&dev);
+        if (st) return st;
+        device_ = dev->device;
+        cus_ = dev->cus;
+        in_place_ = (c.flags & PPC_SERVE_IN_PLACE) != 0;
+        if (!in_place_ && c.arena_bytes) PPC_HIP(hipMalloc(&arena_, c.arena_bytes));
+        max_chunks_ = c.max_batch + (uint32_t)std::min<uint64_t>(c.arena_bytes / kCopyChunk, 1u << 26);
+        streams_.resize(c.streams, nullptr);
+        plans_.resize(c.streams, nullptr);
+        for (uint32_t i = 0; i < c.streams; ++i) {
+            PPC_HIP(hipStreamCreateWithFlags(&streams_[i], hipStreamNonBlocking));
+            ppc_workload_hint hint{c.max_batch, 0};
+            st = ppc_plan_create(&hint, &plans_[i]);
+            if (st) return st;
+        }
+        slots_.resize((size_t)c.streams * 2);
+        for (size_t i = 0; i < slots_.size(); ++i) {
+            Slot& s = slots_[i];
+            s.stream = (int)(i % c.streams);
+            PPC_HIP(hipMalloc(&s.d_descs, sizeof(ppc_desc) * c.max_batch));
+            PPC_HIP(hipMalloc(&s.d_counts, 256ull * c.max_batch));
+            PPC_HIP(hipHostMalloc(&s.h_descs, sizeof(ppc_desc) * c.max_batch));
+            PPC_HIP(hipHostMalloc(&s.h_counts, 256ull * c.max_batch));
+            if (!in_place_) {
+                PPC_HIP(hipMalloc(&s.d_chunks, sizeof(CopyChunk) * max_chunks_));
+                PPC_HIP(hipHostMalloc(&s.h_chunks, sizeof(CopyChunk) * max_chunks_));
+            }
+            PPC_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+        }
+        return PPC_OK;
+    }
+
+    ~HipExecutor() override {
+        wait_all();
+        for (Slot& s : slots_) {
+            if (s.done) (void)hipEventDestroy(s.done);
+            if (s.d_descs) (void)hipFree(s.d_descs);
+            if (s.d_counts) (void)hipFree(s.d_counts);
+            if (s.d_chunks) (void)hipFree(s.d_chunks);
+            if (s.h_descs) (void)hipHostFree(s.h_descs);
+            if (s.h_counts) (void)hipHostFree(s.h_counts);
+            if (s.h_chunks) (void)hipHostFree(s.h_chunks);
+        }
+        for (ppc_plan* p : plans_) ppc_plan_destroy(p);
+        for (hipStream_t s : streams_)
+            if (s) (void)hipStreamDestroy(s);
+        if (arena_) (void)hipFree(arena_);
+    }
+
+    void wait_all() override {
+        for (hipStream_t s : streams_)
+            if (s) (void)hipStreamSynchronize(s);
+    }
+
+    size_t capacity() const override { return slots_.size(); }
+
+    int launch(const std::vector<Admitted>& items, uint64_t* handle) override {
+        size_t si = slots_.size();
+        for (size_t j = 0; j < slots_.size(); ++j) {
+            const size_t i = (next_ + j) % slots_.size();
+            if (!slots_[i].busy) {
+                si = i;
+                break;
+            }
+        }
+        if (si == slots_.size()) return PPC_ERR_STATE;
+        next_ = (si + 1) % slots_.size();
+        Slot& s = slots_[si];
+        const uint32_t n = (uint32_t)items.size();
+        hipStream_t st = streams_[s.stream];
+        uint32_t nchunks = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            const Admitted& a = items[i];
+            const uint8_t* src = (const uint8_t*)a.r.src;
+            uint8_t* dst = in_place_ ? nullptr : (uint8_t*)arena_ + a.off;
+            if (!in_place_) {
+                for (uint64_t o = 0; o < a.bytes; o += kCopyChunk) {
+                    if (nchunks == max_chunks_) return PPC_ERR_ARG;
+                    s.h_chunks[nchunks++] = {src + o, dst + o, std::min(kCopyChunk, a.bytes - o)};
+                }
+            }
+            s.h_descs[i] = {in_place_ ? a.r.src : (const void*)dst, a.r.n, a.r.k, 0,
+                            s.d_counts + 32ull * i};
+        }
+        if (nchunks) {
+            PPC_HIP(hipMemcpyAsync(s.d_chunks, s.h_chunks, sizeof(CopyChunk) * nchunks,
+                                   hipMemcpyHostToDevice, st));
+            const uint32_t grid = std::min<uint32_t>(nchunks, (uint32_t)cus_ * 8);
+            void* args[] = {&s.d_chunks, &nchunks};
+            PPC_HIP(hipLaunchKernel((const void*)copy_chunks, dim3(grid), dim3(256), args, 0, st));
+        }
+        PPC_HIP(hipMemcpyAsync(s.d_descs, s.h_descs, sizeof(ppc_desc) * n, hipMemcpyHostToDevice,
+                               st));
+        PPC_HIP(hipMemsetAsync(s.d_counts, 0, 256ull * n, st));
+        const int bst = pospopcnt_batch(plans_[s.stream], s.d_descs, n, st);
+        if (bst) return bst;
+        PPC_HIP(hipMemcpyAsync(s.h_counts, s.d_counts, 256ull * n, hipMemcpyDeviceToHost, st));
+        PPC_HIP(hipEventRecord(s.done, st));
+        s.busy = true;
+        s.n = n;
+        *handle = si;
+        return PPC_OK;
+    }
+
+    int poll(uint64_t h, bool* done) override {
+        const hipError_t e = hipEventQuery(slots_[h].done);
+        if (e == hipSuccess) {
+            *done = true;
+            return PPC_OK;
+        }
+        *done = false;
+        if (e == hipErrorNotReady) return PPC_OK;
+        return fail_hip(e);
+    }
+
+    int results(uint64_t h, uint64_t* counts) override {
+        memcpy(counts, slots_[h].h_counts, 256ull * slots_[h].n);
+        return PPC_OK;
+    }
+
+    int release(uint64_t h) override {
+        slots_[h].busy = false;
+        return PPC_OK;
+    }
+
+  private:
+    ppc_server_config cfg_{};
+    int device_ = -1, cus_ = 0;
+    bool in_place_ = false;
+    void* arena_ = nullptr;
+    uint32_t max_chunks_ = 0;
+    std::vector<hipStream_t> streams_;
+    std::vector<ppc_plan*> plans_;
+    std::vector<Slot> slots_;
+    size_t next_ = 0;
+};
+
+static int check_server_config(const ppc_server_config& c) {
+    if (c.max_requests < 1 || c.max_requests > kMaxServerRequests) return PPC_ERR_ARG;
+    if (c.max_batch < 1 || c.max_batch > kMaxServerBatch) return PPC_ERR_ARG;
+    if (c.streams < 1 || c.streams > 8) return PPC_ERR_ARG;
+    if (c.flags & ~(uint32_t)(PPC_SERVE_IN_PLACE | PPC_SERVE_FIFO_BYPASS)) return PPC_ERR_ARG;
+    return PPC_OK;
+}
+
+}  // namespace ppc
+
+using namespace ppc;
+
+struct ppc_server {
+    struct Inflight {
+        uint64_t handle;
+        std::vector<Admitted> items;
+        double launched;
+    };
+    struct Waiting {
+        ppc_request r;
+        uint64_t bytes;
+    };
+
+    ppc_server_config cfg{};
+    std::unique_ptr<Executor> exec;
+    Arena arena{0};
+    std::deque<Waiting> queue;
+    std::vector<Admitted> admitted;  // admitted, not yet launched
+    std::vector<Inflight> inflight;
+    std::deque<ppc_completion> done;
+    uint64_t slots = 0;  // requests admitted and not yet completed
+    ppc_server_stats stats{};
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    std::vector<uint64_t> counts;
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    void complete(const ppc_request& r, int status, uint32_t batch, double admitted_t,
+                  double launched_t, const uint64_t* c) {
+        ppc_completion x;
+        memset(&x, 0, sizeof(x));
+        x.tag = r.tag;
+        x.status = status;
+        x.batch = batch;
+        x.arrival = r.arrival;
+        x.admitted = admitted_t;
+        x.launched = launched_t;
+        x.completed = now();
+        if (c && status == PPC_OK) memcpy(x.counts, c, sizeof(uint64_t) * r.k);
+        done.push_back(x);
+        ++stats.completed;
+    }
+
+    void finish(Inflight& f, int status) {
+        const uint32_t n = (uint32_t)f.items.size();
+        if (!status) {
+            counts.resize(32ull * n);
+            status = exec->results(f.handle, counts.data());
+        }
+        for (uint32_t i = 0; i < n; ++i) {
+            const Admitted& a = f.items[i];
+            complete(a.r, status, n, a.admitted, f.launched, status ? nullptr : &counts[32ull * i]);
+            arena.release(a.off, a.bytes);
+            if (!status) stats.bytes_counted += a.bytes;
+        }
+        slots -= n;
+        exec->release(f.handle);
+    }
+
+    uint32_t reap() {
+        uint32_t n = 0;
+        for (size_t i = 0; i < inflight.size();) {
+            bool fin = false;
+            const int st = exec->poll(inflight[i].handle, &fin);
+            if (st || fin) {
+                n += (uint32_t)inflight[i].items.size();
+                finish(inflight[i], st);
+                inflight.erase(inflight.begin() + (long)i);
+            } else {
+                ++i;
+            }
+        }
+        return n;
+    }
+
+    void admit() {
+        const double t = now();
+        const bool bypass = (cfg.flags & PPC_SERVE_FIFO_BYPASS) != 0;
+        for (auto it = queue.begin(); it != queue.end() && slots < cfg.max_requests;) {
+            uint64_t off = 0;
+            if (arena.alloc(it->bytes, &off)) {
+                admitted.push_back({it->r, it->bytes, off, t});
+                ++slots;
+                ++stats.admitted;
+                it = queue.erase(it);
+            } else if (bypass) {
+                ++it;
+            } else {
+                break;
+            }
+        }
+    }
+
+    uint32_t launch() {
+        if (admitted.empty() || inflight.size() >= exec->capacity()) return 0;
+        const size_t n = std::min<size_t>(admitted.size(), cfg.max_batch);
+        Inflight f;
+        f.items.assign(admitted.begin(), admitted.begin() + (long)n);
+        admitted.erase(admitted.begin(), admitted.begin() + (long)n);
+        f.launched = now();
+        const int st = exec->launch(f.items, &f.handle);
+        ++stats.launches;
+        if (st) {
+            for (const Admitted& a : f.items) {
+                complete(a.r, st, (uint32_t)n, a.admitted, f.launched, nullptr);
+                arena.release(a.off, a.bytes);
+            }
+            slots -= n;
+            return (uint32_t)n;
+        }
+        inflight.push_back(std::move(f));
+        return (uint32_t)n;
+    }
+
+    void note() {
+        stats.queued_now = queue.size();
+        stats.inflight_now = slots;
+        stats.max_queued = std::max<uint64_t>(stats.max_queued, queue.size());
+        stats.max_inflight = std::max<uint64_t>(stats.max_inflight, slots);
+        stats.arena_used_now = arena.used();
+        stats.arena_peak = arena.peak();
+    }
+};
+
+static int server_init(const ppc_server_config* config, ppc_server** out) {
+    if (!config || !out) return PPC_ERR_NULL;
+    *out = nullptr;
+    return check_server_config(*config);
+}
+
+extern "C" {
+
+int ppc_server_create(const ppc_server_config* config, ppc_server** out) {
+    int st = server_init(config, out);
+    if (st) return st;
+    auto ex = std::make_unique<HipExecutor>();
+    st = ex->init(*config);
+    if (st) return st;  // the executor's destructor frees what init allocated
+    ppc_server* s = new ppc_server();
+    s->cfg = *config;
+    s->arena = Arena(config->arena_bytes);
+    s->exec = std::move(ex);
+    *out = s;
+    return PPC_OK;
+}
+
+int ppc_server_create_with_executor(const ppc_server_config* config, const ppc_executor_ops* ops,
+                                    void* user, ppc_server** out) {
+    int st = server_init(config, out);
+    if (st) return st;
+    if (!ops || !ops->launch || !ops->poll || !ops->results || !ops->release) return PPC_ERR_NULL;
+    ppc_server* s = new ppc_server();
+    s->cfg = *config;
+    s->arena = Arena(config->arena_bytes);
+    s->exec = std::make_unique<CallbackExecutor>(*ops, user, (size_t)config->streams * 2);
+    *out = s;
+    return PPC_OK;
+}
+
+int ppc_server_destroy(ppc_server* s) {
+    if (!s) return PPC_OK;
+    s->exec->wait_all();
+    delete s;
+    return PPC_OK;
+}
+
+double ppc_server_now(const ppc_server* s) { return s ? s->now() : 0.0; }
+
+int ppc_server_submit(ppc_server* s, const ppc_request* reqs, uint32_t n) {
+    if (!s) return PPC_ERR_NULL;
+    if (n && !reqs) return PPC_ERR_NULL;
+    for (uint32_t i = 0; i < n; ++i) {
+        const ppc_request& r = reqs[i];
+        ++s->stats.submitted;
+        int st = PPC_OK;
+        uint64_t bytes = 0;
+        if (r.k != 8 && r.k != 16 && r.k != 32) st = PPC_ERR_WIDTH;
+        else if (r.reserved) st = PPC_ERR_ARG;
+        else if (r.n > UINT64_MAX / (r.k / 8)) st = PPC_ERR_ARG;
+        else if (r.n && !r.src) st = PPC_ERR_NULL;
+        else {
+            bytes = r.n * (r.k / 8);
+            if (Arena::granules(bytes) > s->arena.size()) st = PPC_ERR_BUDGET;
+        }
+        if (st) {
+            ++s->stats.rejected;
+            s->complete(r, st, 0, 0.0, 0.0, nullptr);
+        } else if (bytes == 0) {
+            static const uint64_t zeros[32] = {0};
+            s->complete(r, PPC_OK, 0, r.arrival, r.arrival, zeros);
+        } else {
+            s->queue.push_back({r, bytes});
+        }
+    }
+    s->note();
+    return PPC_OK;
+}
+
+int ppc_server_progress(ppc_server* s, uint32_t* launched, uint32_t* completed) {
+    if (!s) return PPC_ERR_NULL;
+    const uint32_t c = s->reap();
+    s->admit();
+    const uint32_t l = s->launch();
+    s->note();
+    if (launched) *launched = l;
+    if (completed) *completed = c;
+    return PPC_OK;
+}
+
+int ppc_server_take_completions(ppc_server* s, ppc_completion* out, uint32_t cap,
+                                uint32_t* n_out) {
+    if (!s || !n_out) return PPC_ERR_NULL;
+    if (cap && !out) return PPC_ERR_NULL;
+    uint32_t n = 0;
+    while (n < cap && !s->done.empty()) {
+        out[n++] = s->done.front();
+        s->done.pop_front();
+    }
+    *n_out = n;
+    return PPC_OK;
+}
+
+int ppc_server_get_stats(const ppc_server* s, ppc_server_stats* out) {
+    if (!s || !out) return PPC_ERR_NULL;
+    *out = s->stats;
+    return PPC_OK;
+}
+
+int ppc_server_run_trace(ppc_server* s, const ppc_request* reqs, uint32_t n, ppc_completion* out) {
+    if (!s) return PPC_ERR_NULL;
+    if (n && (!reqs || !out)) return PPC_ERR_NULL;
+    for (uint32_t i = 1; i < n; ++i)
+        if (reqs[i].arrival < reqs[i - 1].arrival) return PPC_ERR_ARG;
+    // Requests are submitted with their index as tag; completions are put back in
+    // place with the caller's tag.
+    const double start = s->now();
+    uint32_t next = 0, finished = 0;
+    double last_change = start;
+    std::vector<ppc_completion> buf(256);
+    while (finished < n) {
+        const double t = s->now();
+        uint32_t sub = 0;
+        while (next < n && reqs[next].arrival <= t - start) {
+            ppc_request r = reqs[next];
+            r.arrival += start;
+            r.tag = next;
+            ppc_server_submit(s, &r, 1);
+            ++next;
+            ++sub;
+        }
+        uint32_t l = 0, c = 0;
+        ppc_server_progress(s, &l, &c);
+        uint32_t got = 0;
+        ppc_server_take_completions(s, buf.data(), (uint32_t)buf.size(), &got);
+        for (uint32_t i = 0; i < got; ++i) {
+            const uint64_t idx = buf[i].tag;
+            out[idx] = buf[i];
+            out[idx].tag = reqs[idx].tag;
+        }
+        finished += got;
+        if (sub || l || c || got) {
+            last_change = s->now();
+        } else if (s->now() - last_change > kStallSeconds) {
+            return PPC_ERR_STATE;  // nothing moved for too long: a launch never finished
+        } else if (next < n && s->slots == 0 && s->queue.empty()) {
+            // idle until the next arrival: yield instead of spinning hard
+            const double wait = reqs[next].arrival - (s->now() - start);
+            if (wait > 200e-6) std::this_thread::sleep_for(std::chrono::microseconds(50));
+        }
+    }
+    return PPC_OK;
+}
+
+}  // extern "C"

@@ -217,3 +217,46 @@ def fill_streams(arena: np.ndarray, streams: StreamSet, starts: np.ndarray, seed
             fill(arena[s:s + b], Dist.bernoulli(float(streams.ps[i])), seed, stream=i,
                  threads=threads if b > (1 << 22) else 1)
     return arena
+
+
+@dataclass
+class RequestTrace:
+    """A serving trace: arrival times (s), lengths (words), widths, the source pool
+    of every request (pool index into `pools`) and its byte offset there."""
+
+    arrival: np.ndarray
+    lengths: np.ndarray
+    ks: np.ndarray
+    pool: np.ndarray
+    offset: np.ndarray
+    pools: list  # [(k, Dist)] in pool-index order
+
+    @property
+    def nbytes(self) -> np.ndarray:
+        return self.lengths * (self.ks.astype(np.uint64) // 8)
+
+
+def serving_trace(rate: float, duration_s: float, seed: int, min_log2: int = 10,
+                  max_log2: int = 26, pool_bytes: int = 1 << 29,
+                  zipf_s: float = 1.1) -> RequestTrace:
+    """Poisson arrivals at `rate`; lengths log-uniform in [2^min_log2, 2^max_log2]
+    words; k uniform over {8, 16, 32}; input one-hot Zipf(zipf_s) or Bernoulli(1/2)
+    by a fair coin; each request reads a 256-byte aligned window of a pool of its
+    (k, distribution), pool_bytes long."""
+    t = poisson_arrivals(rate, duration_s, seed)
+    m = len(t)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    u = rng.random(m)
+    lengths = np.rint(np.exp((min_log2 + u * (max_log2 - min_log2)) * math.log(2.0)))
+    lengths = lengths.astype(np.uint64)
+    ks = rng.choice(np.array([8, 16, 32], dtype=np.int32), size=m)
+    onehot = rng.random(m) < 0.5
+    pools = [(k, Dist.onehot(k, zipf_s)) for k in (8, 16, 32)] + \
+            [(k, Dist.uniform()) for k in (8, 16, 32)]
+    pool = np.where(onehot, 0, 3) + np.searchsorted([8, 16, 32], ks)
+    nb = lengths * (ks.astype(np.uint64) // 8)
+    if int(nb.max(initial=0)) > pool_bytes:
+        raise ValueError("pool smaller than the largest request")
+    room = (pool_bytes - nb) // 256
+    offset = (rng.integers(0, np.iinfo(np.int64).max, size=m) % (room + 1)) * 256
+    return RequestTrace(t, lengths, ks, pool.astype(np.int32), offset.astype(np.uint64), pools)

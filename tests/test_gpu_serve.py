@@ -1,0 +1,86 @@
+"""GPU serving: requests replayed through the continuous-batching server give, for
+every request, the oracle's counts and the counts of the same input counted
+alone (tolerance 0), under memory-budget pressure and with launches
+overlapping on several streams."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1911_02696_amd import api
+from paper_1911_02696_amd import inputs as I
+from paper_1911_02696_amd import serve as S
+
+from gpu_util import oracle_counts, say
+
+pytestmark = pytest.mark.gpu
+SEED = I.BASE_SEED + 4
+POOL = 64 << 20
+
+
+@pytest.fixture(scope="module")
+def workload():
+    trace = I.serving_trace(200_000, 0.015, SEED, min_log2=4, max_log2=22, pool_bytes=POOL)
+    pools = S.Pools(trace, POOL, SEED)
+    return trace, pools, pools.requests(trace)
+
+
+def expected(trace, pools, i):
+    n, k = int(trace.lengths[i]), int(trace.ks[i])
+    return oracle_counts(pools.host_bytes(trace, i), n, k)
+
+
+def alone(req):
+    out = torch.zeros(32, dtype=torch.int64, device="cuda")
+    api.pospopcnt_ptr(int(req["src"]), int(req["n"]), int(req["k"]), out.data_ptr())
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("in_place", [False, True], ids=["copy", "in_place"])
+def test_served_counts_equal_oracle_and_alone(workload, in_place):
+    trace, pools, reqs = workload
+    m = len(reqs)
+    say(f"serve: {m} requests, {trace.nbytes.sum() / 1e9:.2f} GB, in_place={in_place}")
+    arena = 96 << 20  # far below the total: requests wait for memory
+    srv = S.Server(arena, max_requests=512, max_batch=128, streams=4, in_place=in_place)
+    comps = srv.run_trace(reqs)
+    st = srv.stats()
+    srv.close()
+    assert (comps["status"] == 0).all(), np.unique(comps["status"])
+    assert (comps["tag"] == np.arange(m)).all()
+    assert st["arena_peak"] <= arena and st["max_queued"] > 0 and st["launches"] > 1
+    assert st["bytes_counted"] == int(trace.nbytes.sum())
+    rng = np.random.Generator(np.random.PCG64(SEED))
+    sample = set(rng.choice(m, size=min(m, 400), replace=False).tolist())
+    sample |= set(np.argsort(trace.nbytes)[-20:].tolist())
+    for i in range(m):
+        k = int(trace.ks[i])
+        exp = expected(trace, pools, i)
+        assert (comps["counts"][i][:k].astype(np.int64) == exp).all(), f"request {i}"
+        if i in sample:
+            assert (alone(reqs[i])[:k] == exp).all(), f"request {i} alone"
+    lat = S.latency_summary(comps)
+    assert lat["ok"] == m
+    say(f"serve latency {lat}")
+
+
+def test_request_larger_than_budget_is_rejected(workload):
+    trace, pools, reqs = workload
+    big = int(np.argmax(trace.nbytes))
+    srv = S.Server(int(trace.nbytes[big]) - 1024, max_requests=8, max_batch=8, streams=1)
+    comps = srv.run_trace(reqs[[big]])
+    srv.close()
+    assert comps["status"][0] == 6
+
+
+def test_many_small_requests_one_stream(workload):
+    trace, pools, reqs = workload
+    small = np.nonzero(trace.nbytes < 4096)[0][:500]
+    r = reqs[small].copy()
+    r["arrival"] = 0.0
+    srv = S.Server(1 << 24, max_requests=64, max_batch=16, streams=1)
+    comps = srv.run_trace(r)
+    srv.close()
+    for j, i in enumerate(small):
+        k = int(trace.ks[i])
+        assert (comps["counts"][j][:k].astype(np.int64) == expected(trace, pools, i)).all()
+    assert comps["batch"].max() <= 16
