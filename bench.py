@@ -291,6 +291,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 20,000-stream batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--legs", default="single,batched,serving",
+                    help="comma-separated subset of single,batched,serving to run (the JSON "
+                         "line is printed only when the single leg runs)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-reference", type=int, default=0, metavar="BYTES",
@@ -316,6 +319,21 @@ def main():
         print(json.dumps({"copy_reference_bytes": args.copy_reference, "copies": args.steps,
                           "read_bytes_per_copy": args.copy_reference,
                           "write_bytes_per_copy": args.copy_reference}))
+        return
+
+    legs = set(args.legs.split(","))
+    if not legs <= {"single", "batched", "serving"}:
+        ap.error("--legs takes single, batched and serving")
+    args.no_batched |= "batched" not in legs
+    args.no_serving |= "serving" not in legs
+    if "single" not in legs:
+        torch.cuda.set_device(0)
+        out = {}
+        if not args.no_batched:
+            out["batched"] = batched_leg(args, torch, api)[0]
+        if not args.no_serving:
+            out["serving"] = serving_leg(args, torch, api)[0]
+        print(json.dumps(out), flush=True)
         return
 
     k, n, dist, desc = WORKLOADS[args.workload]

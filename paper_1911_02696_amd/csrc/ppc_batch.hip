@@ -11,8 +11,8 @@
 //
 // Two kernels per call:
 //   batch_prep  (one block): validates the descriptors, scans their weights into
-//               cum[0..m] and, for every block, finds the first stream its share
-//               touches (binary search), into first[0..G);
+//               cum[0..m] and, for every block, records the first position its
+//               share touches, into first[0..G);
 //   batch_main  (G blocks): each block walks the streams of its share; for each
 //               it runs the CSA core of the single-stream kernel over its piece of
 //               the body (the block's waves take its 64-lane tiles in turn), the
@@ -158,42 +158,97 @@ __device__ __forceinline__ uint32_t stream_at(uint32_t pos, uint32_t m) {
     return (uint32_t)(((uint64_t)pos * kVisitPrime) % m);
 }
 
+// Weight of one descriptor on the axis (0 for empty or invalid ones).
+__device__ __forceinline__ uint64_t weight_of(const ppc_desc& d, uint64_t weight, uint32_t* bad) {
+    uint64_t nb;
+    if (!desc_valid(d, &nb)) {
+        ++*bad;
+        return 0;
+    }
+    return nb ? weight + split_dev(d.ptr, nb, (int)d.k).units : 0;
+}
+
+constexpr int kPrepPerThread = 4;
+constexpr uint32_t kPrepLdsPositions = kPrepThreads * kPrepPerThread;  // cum kept in LDS up to here
+
+// Two passes in one block.  Pass 1 writes the weight of every position into cum
+// (four descriptor loads in flight per thread).  Pass 2 turns cum into its
+// exclusive prefix sums, four consecutive positions per thread; up to 4096
+// positions the prefix array is also kept in LDS.  Then every block's first
+// position -- the last one starting at or before the block's share -- is found
+// by binary search (in LDS when it holds the array).  With zero_counts, the
+// counters of every valid descriptor are cleared first (for callers whose
+// descriptors own distinct counters and want fresh counts, like the serving
+// loop; the public entry point adds into counters and never sets it).
 __global__ void __launch_bounds__(kPrepThreads)
 batch_prep(const ppc_desc* __restrict__ descs, uint32_t m, uint64_t weight, uint64_t* cum,
-           uint32_t* first, uint32_t G, uint32_t* rejected) {
+           uint32_t* first, uint32_t G, uint32_t* rejected, int zero_counts) {
+    constexpr int R = kPrepPerThread;
     __shared__ uint64_t sh[kPrepThreads / kWave];
+    __shared__ uint64_t lcum[kPrepLdsPositions + 1];
     __shared__ uint32_t bad_total;
     if (threadIdx.x == 0) bad_total = 0;
-    uint64_t carry = 0;
+    const uint32_t T = blockDim.x;
+    const bool in_lds = m <= kPrepLdsPositions;
+    uint64_t local = 0;
     uint32_t bad = 0;
-    for (uint32_t c0 = 0; c0 < m; c0 += blockDim.x) {
-        const uint32_t i = c0 + threadIdx.x;
-        uint64_t w = 0;
-        if (i < m) {
-            const ppc_desc d = descs[stream_at(i, m)];
-            uint64_t nb;
-            if (desc_valid(d, &nb)) {
-                if (nb) w = weight + split_dev(d.ptr, nb, (int)d.k).units;
-            } else {
-                ++bad;
+    for (uint32_t c0 = 0; c0 < m; c0 += T * R) {
+        ppc_desc d[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t i = c0 + r * T + threadIdx.x;
+            if (i < m) d[r] = descs[stream_at(i, m)];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t i = c0 + r * T + threadIdx.x;
+            if (i < m) {
+                const uint64_t w = weight_of(d[r], weight, &bad);
+                cum[i] = w;
+                local += w;
+                if (zero_counts && w)  // valid and non-empty: counts checked by desc_valid
+                    for (uint32_t p = 0; p < d[r].k; ++p) d[r].counts[p] = 0;
             }
         }
-        uint64_t tot;
-        const uint64_t ex = block_exclusive_scan(w, &tot, sh);
-        if (i < m) cum[i] = carry + ex;
-        carry += tot;
     }
-    if (threadIdx.x == 0) cum[m] = carry;
+    uint64_t total;
+    (void)block_exclusive_scan(local, &total, sh);  // barriers: pass-1 writes are visible
+    uint64_t carry = 0;
+    for (uint32_t c0 = 0; c0 < m; c0 += T * R) {
+        const uint32_t p0 = c0 + threadIdx.x * R;
+        uint64_t w[R], sum = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            w[r] = p0 + r < m ? cum[p0 + r] : 0;
+            sum += w[r];
+        }
+        uint64_t round_total;
+        uint64_t run = carry + block_exclusive_scan(sum, &round_total, sh);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (p0 + r < m) {
+                cum[p0 + r] = run;
+                if (in_lds) lcum[p0 + r] = run;
+                run += w[r];
+            }
+        }
+        carry += round_total;
+    }
+    if (threadIdx.x == 0) {
+        cum[m] = total;
+        if (in_lds) lcum[m] = total;
+    }
     if (bad) atomicAdd(&bad_total, bad);
     __syncthreads();
     if (threadIdx.x == 0) rejected[0] = bad_total;
-    // Start stream of every block's share: the last s < m with cum[s] <= lo.
-    for (uint32_t b = threadIdx.x; b < G; b += blockDim.x) {
-        const uint64_t lo = share_lo(b, carry, G);
-        uint32_t l = 0, h = m;
+    const uint64_t base = total / G, extra = total % G;
+    for (uint32_t b = threadIdx.x; b < G; b += T) {
+        const uint64_t lo = (uint64_t)b * base + (b < extra ? b : extra);
+        uint32_t l = 0, h = m;  // last position l < m with cum[l] <= lo
         while (h - l > 1) {
             const uint32_t mid = l + (h - l) / 2;
-            if (cum[mid] <= lo) l = mid; else h = mid;
+            const uint64_t c = in_lds ? lcum[mid] : cum[mid];
+            if (c <= lo) l = mid; else h = mid;
         }
         first[b] = l;
     }
@@ -319,11 +374,12 @@ static int check_config(const ppc_batch_config& c) {
 }
 
 static int enqueue(ppc_plan* pl, const ppc_desc* descs, uint32_t m, hipStream_t s,
-                   unsigned long long* sink) {
+                   unsigned long long* sink, int zero_counts = 0) {
     const ppc_batch_config& c = pl->cfg;
     uint32_t G = (uint32_t)(c.blocks_per_cu * pl->cus);
     uint64_t weight = (uint64_t)c.stream_weight;
-    void* pargs[] = {(void*)&descs, &m, &weight, &pl->cum, &pl->first, &G, &pl->rejected};
+    void* pargs[] = {(void*)&descs, &m,       &weight,       &pl->cum,
+                     &pl->first,    &G,       &pl->rejected, &zero_counts};
     PPC_HIP(hipLaunchKernel((const void*)batch_prep, dim3(1), dim3(kPrepThreads), pargs, 0, s));
     const uint64_t* cum = pl->cum;
     const uint32_t* first = pl->first;
@@ -349,6 +405,18 @@ static int device_of(ppc_plan* pl) {
 }  // namespace ppc
 
 using namespace ppc;
+
+namespace ppc {
+// The batched count with every valid descriptor's counters cleared first, for
+// callers whose descriptors own distinct counters (the serving executor); never
+// captured into a graph.
+int batch_fresh(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s) {
+    if (!pl || !d_descs) return PPC_ERR_NULL;
+    if (m == 0) return PPC_OK;
+    if (m > pl->max_streams) return PPC_ERR_ARG;
+    return enqueue(pl, d_descs, m, s, nullptr, 1);
+}
+}  // namespace ppc
 
 extern "C" {
 

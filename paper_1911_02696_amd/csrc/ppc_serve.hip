@@ -12,10 +12,11 @@
 // launches on different streams overlap on the device.
 //
 // GPU executor: a launch on stream s (launch slots rotate over the streams, two
-// per stream) enqueues, in order: the copy of every request's input from its
-// source into its slab (one kernel over 256 KiB chunks), the descriptor table,
-// zeroing of the launch's counts, the batched count (one plan per stream), the
-// copy of the counts to pinned host memory, and an event the scheduler polls.
+// per stream) enqueues, in order: one host-to-device copy of the descriptor table
+// and the copy segments, the copy of every request's input from its source into
+// its slab (one kernel, byte-balanced over its blocks), the batched count (one plan per
+// stream; its prefix kernel clears the launch's counters), the copy of the counts
+// to pinned host memory, and an event the scheduler polls.
 #include <string.h>
 
 #include <algorithm>
@@ -32,7 +33,6 @@
 namespace ppc {
 
 constexpr uint64_t kGranule = 256;
-constexpr uint64_t kCopyChunk = 256 << 10;
 constexpr uint32_t kMaxServerRequests = 1u << 20;
 constexpr uint32_t kMaxServerBatch = 65536;
 constexpr double kStallSeconds = 120.0;  // run_trace gives up after this long without progress
@@ -133,44 +133,78 @@ class CallbackExecutor : public Executor {
     size_t cap_;
 };
 
-struct CopyChunk {
+// One request's input copy: `units` 16-byte units from src to dst, starting at
+// unit `start` of the launch's copy axis.  When src or dst is not 16-byte
+// aligned the unit is copied byte by byte (never past `bytes`).
+struct CopySeg {
     const uint8_t* src;
     uint8_t* dst;
     uint64_t bytes;
+    uint64_t start;
 };
 
-// Copies every chunk; a block takes chunks in turn.  16-byte units when source
-// and destination are both 16-byte aligned, bytes otherwise.
-__global__ void __launch_bounds__(256) copy_chunks(const CopyChunk* __restrict__ chunks,
-                                                   uint32_t n) {
-    for (uint32_t c = blockIdx.x; c < n; c += gridDim.x) {
-        const CopyChunk ch = chunks[c];
-        if ((((uintptr_t)ch.src | (uintptr_t)ch.dst) & 15u) == 0) {
-            const uint64_t units = ch.bytes / 16;
-            const u32x4* s = (const u32x4*)ch.src;
-            u32x4* d = (u32x4*)ch.dst;
-            for (uint64_t u = threadIdx.x; u < units; u += blockDim.x) d[u] = stream_load(s + u);
-            for (uint64_t b = units * 16 + threadIdx.x; b < ch.bytes; b += blockDim.x)
-                ch.dst[b] = ch.src[b];
+__device__ __forceinline__ uint64_t seg_units(const CopySeg& s) { return (s.bytes + 15) / 16; }
+
+// Copies every segment of a launch.  Block b takes the b-th of G equal slices of
+// the launch's units (segments laid end to end), so a large request is spread
+// over all blocks and small ones share blocks; each thread keeps four 16-byte
+// loads in flight.  Aligned segments may write the rest of their last unit: the
+// destination slab is rounded up to 256 bytes, and the source unit holding the
+// last byte lies within that byte's page.
+__global__ void __launch_bounds__(256) copy_segments(const CopySeg* __restrict__ segs, uint32_t n,
+                                                     uint64_t total) {
+    const uint64_t G = gridDim.x, b = blockIdx.x, T = blockDim.x;
+    const uint64_t base = total / G, extra = total % G;
+    const uint64_t lo = b * base + (b < extra ? b : extra);
+    const uint64_t hi = lo + base + (b < extra ? 1 : 0);
+    if (lo >= hi) return;
+    uint32_t l = 0, h = n;  // last segment starting at or before lo
+    while (h - l > 1) {
+        const uint32_t mid = l + (h - l) / 2;
+        if (segs[mid].start <= lo) l = mid; else h = mid;
+    }
+    for (uint32_t i = l; i < n; ++i) {
+        const CopySeg sg = segs[i];
+        if (sg.start >= hi) break;
+        const uint64_t units = seg_units(sg);
+        const uint64_t u0 = lo > sg.start ? lo - sg.start : 0;
+        const uint64_t u1 = hi < sg.start + units ? hi - sg.start : units;
+        if (u0 >= u1) continue;
+        if ((((uintptr_t)sg.src | (uintptr_t)sg.dst) & 15u) == 0) {
+            const u32x4* src = (const u32x4*)sg.src;
+            u32x4* dst = (u32x4*)sg.dst;
+            uint64_t u = u0 + threadIdx.x;
+            for (; u + 3 * T < u1; u += 4 * T) {
+                const u32x4 a = stream_load(src + u), c = stream_load(src + u + T),
+                            d = stream_load(src + u + 2 * T), e = stream_load(src + u + 3 * T);
+                dst[u] = a;
+                dst[u + T] = c;
+                dst[u + 2 * T] = d;
+                dst[u + 3 * T] = e;
+            }
+            for (; u < u1; u += T) dst[u] = stream_load(src + u);
         } else {
-            for (uint64_t b = threadIdx.x; b < ch.bytes; b += blockDim.x) ch.dst[b] = ch.src[b];
+            for (uint64_t u = u0 + threadIdx.x; u < u1; u += T)
+                for (uint64_t x = u * 16; x < u * 16 + 16 && x < sg.bytes; ++x) sg.dst[x] = sg.src[x];
         }
     }
 }
 
 class HipExecutor : public Executor {
   public:
+    // One launch's buffers.  Descriptors and copy segments share one staging area
+    // (and one device area) so that a single host-to-device copy carries both.
     struct Slot {
         int stream = 0;
         bool busy = false;
         uint32_t n = 0;
-        ppc_desc* d_descs = nullptr;
+        char* d_meta = nullptr;  // [descs: max_batch][segments: max_batch]
         uint64_t* d_counts = nullptr;
-        CopyChunk* d_chunks = nullptr;
-        ppc_desc* h_descs = nullptr;
+        char* h_meta = nullptr;
         uint64_t* h_counts = nullptr;
-        CopyChunk* h_chunks = nullptr;
         hipEvent_t done = nullptr;
+        ppc_desc* h_descs() { return (ppc_desc*)h_meta; }
+        ppc_desc* d_descs() { return (ppc_desc*)d_meta; }
     };
 
     int init(const ppc_server_config& c) {
@@ -182,7 +216,6 @@ class HipExecutor : public Executor {
         cus_ = dev->cus;
         in_place_ = (c.flags & PPC_SERVE_IN_PLACE) != 0;
         if (!in_place_ && c.arena_bytes) PPC_HIP(hipMalloc(&arena_, c.arena_bytes));
-        max_chunks_ = c.max_batch + (uint32_t)std::min<uint64_t>(c.arena_bytes / kCopyChunk, 1u << 26);
         streams_.resize(c.streams, nullptr);
         plans_.resize(c.streams, nullptr);
         for (uint32_t i = 0; i < c.streams; ++i) {
@@ -192,17 +225,15 @@ class HipExecutor : public Executor {
             if (st) return st;
         }
         slots_.resize((size_t)c.streams * 2);
+        seg_base_ = (sizeof(ppc_desc) * c.max_batch + 255) & ~(size_t)255;
+        const size_t meta = seg_base_ + (in_place_ ? 0 : sizeof(CopySeg) * c.max_batch);
         for (size_t i = 0; i < slots_.size(); ++i) {
             Slot& s = slots_[i];
             s.stream = (int)(i % c.streams);
-            PPC_HIP(hipMalloc(&s.d_descs, sizeof(ppc_desc) * c.max_batch));
+            PPC_HIP(hipMalloc(&s.d_meta, meta));
             PPC_HIP(hipMalloc(&s.d_counts, 256ull * c.max_batch));
-            PPC_HIP(hipHostMalloc(&s.h_descs, sizeof(ppc_desc) * c.max_batch));
+            PPC_HIP(hipHostMalloc(&s.h_meta, meta));
             PPC_HIP(hipHostMalloc(&s.h_counts, 256ull * c.max_batch));
-            if (!in_place_) {
-                PPC_HIP(hipMalloc(&s.d_chunks, sizeof(CopyChunk) * max_chunks_));
-                PPC_HIP(hipHostMalloc(&s.h_chunks, sizeof(CopyChunk) * max_chunks_));
-            }
             PPC_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
         }
         return PPC_OK;
@@ -212,12 +243,10 @@ class HipExecutor : public Executor {
         wait_all();
         for (Slot& s : slots_) {
             if (s.done) (void)hipEventDestroy(s.done);
-            if (s.d_descs) (void)hipFree(s.d_descs);
+            if (s.d_meta) (void)hipFree(s.d_meta);
             if (s.d_counts) (void)hipFree(s.d_counts);
-            if (s.d_chunks) (void)hipFree(s.d_chunks);
-            if (s.h_descs) (void)hipHostFree(s.h_descs);
+            if (s.h_meta) (void)hipHostFree(s.h_meta);
             if (s.h_counts) (void)hipHostFree(s.h_counts);
-            if (s.h_chunks) (void)hipHostFree(s.h_chunks);
         }
         for (ppc_plan* p : plans_) ppc_plan_destroy(p);
         for (hipStream_t s : streams_)
@@ -246,31 +275,31 @@ class HipExecutor : public Executor {
         Slot& s = slots_[si];
         const uint32_t n = (uint32_t)items.size();
         hipStream_t st = streams_[s.stream];
-        uint32_t nchunks = 0;
+        CopySeg* h_segs = (CopySeg*)(s.h_meta + seg_base_);
+        uint64_t units = 0;
         for (uint32_t i = 0; i < n; ++i) {
             const Admitted& a = items[i];
-            const uint8_t* src = (const uint8_t*)a.r.src;
             uint8_t* dst = in_place_ ? nullptr : (uint8_t*)arena_ + a.off;
             if (!in_place_) {
-                for (uint64_t o = 0; o < a.bytes; o += kCopyChunk) {
-                    if (nchunks == max_chunks_) return PPC_ERR_ARG;
-                    s.h_chunks[nchunks++] = {src + o, dst + o, std::min(kCopyChunk, a.bytes - o)};
-                }
+                h_segs[i] = {(const uint8_t*)a.r.src, dst, a.bytes, units};
+                units += (a.bytes + 15) / 16;
             }
-            s.h_descs[i] = {in_place_ ? a.r.src : (const void*)dst, a.r.n, a.r.k, 0,
-                            s.d_counts + 32ull * i};
+            s.h_descs()[i] = {in_place_ ? a.r.src : (const void*)dst, a.r.n, a.r.k, 0,
+                              s.d_counts + 32ull * i};
         }
-        if (nchunks) {
-            PPC_HIP(hipMemcpyAsync(s.d_chunks, s.h_chunks, sizeof(CopyChunk) * nchunks,
-                                   hipMemcpyHostToDevice, st));
-            const uint32_t grid = std::min<uint32_t>(nchunks, (uint32_t)cus_ * 8);
-            void* args[] = {&s.d_chunks, &nchunks};
-            PPC_HIP(hipLaunchKernel((const void*)copy_chunks, dim3(grid), dim3(256), args, 0, st));
+        // one copy of the descriptors (and the copy segments right after them)
+        const size_t meta = in_place_ ? sizeof(ppc_desc) * n : seg_base_ + sizeof(CopySeg) * n;
+        PPC_HIP(hipMemcpyAsync(s.d_meta, s.h_meta, meta, hipMemcpyHostToDevice, st));
+        if (units) {
+            const CopySeg* d_segs = (const CopySeg*)(s.d_meta + seg_base_);
+            // about 16 KiB per block, at most 8 blocks per compute unit
+            const uint64_t want = (units + 1023) / 1024;
+            const uint32_t grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)cus_ * 8);
+            void* args[] = {(void*)&d_segs, (void*)&n, &units};
+            PPC_HIP(hipLaunchKernel((const void*)copy_segments, dim3(grid), dim3(256), args, 0, st));
         }
-        PPC_HIP(hipMemcpyAsync(s.d_descs, s.h_descs, sizeof(ppc_desc) * n, hipMemcpyHostToDevice,
-                               st));
-        PPC_HIP(hipMemsetAsync(s.d_counts, 0, 256ull * n, st));
-        const int bst = pospopcnt_batch(plans_[s.stream], s.d_descs, n, st);
+        // counts are cleared by the batch's own prefix kernel
+        const int bst = batch_fresh(plans_[s.stream], s.d_descs(), n, st);
         if (bst) return bst;
         PPC_HIP(hipMemcpyAsync(s.h_counts, s.d_counts, 256ull * n, hipMemcpyDeviceToHost, st));
         PPC_HIP(hipEventRecord(s.done, st));
@@ -306,7 +335,7 @@ class HipExecutor : public Executor {
     int device_ = -1, cus_ = 0;
     bool in_place_ = false;
     void* arena_ = nullptr;
-    uint32_t max_chunks_ = 0;
+    size_t seg_base_ = 0;
     std::vector<hipStream_t> streams_;
     std::vector<ppc_plan*> plans_;
     std::vector<Slot> slots_;

@@ -212,3 +212,19 @@ def test_c4_full_mix():
     say("C4: oracle")
     bt.counts.copy_(torch.from_numpy(got))
     bt.check()
+
+
+@pytest.mark.parametrize("weight", [1, 3, 4096])
+def test_tiny_totals_smaller_than_the_grid(weight):
+    """A few edge-only streams: the weighted axis is shorter than the grid, so most
+    blocks have empty shares."""
+    s = I.StreamSet(np.array([1, 3, 0, 7, 2], np.uint64), np.array([8, 16, 32, 8, 32], np.int32),
+                    np.array([0.5] * 5))
+    bt = Batch(s, SEED + 5)
+    for cfg in (dict(blocks_per_cu=16, block_threads=64), dict(blocks_per_cu=1, block_threads=256)):
+        bt.counts.zero_()
+        plan = B.Plan(5)
+        plan.config = dict(cfg, stream_weight=weight)
+        plan.run(bt.descs)
+        torch.cuda.synchronize()
+        bt.check()

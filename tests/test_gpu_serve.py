@@ -84,3 +84,25 @@ def test_many_small_requests_one_stream(workload):
         k = int(trace.ks[i])
         assert (comps["counts"][j][:k].astype(np.int64) == expected(trace, pools, i)).all()
     assert comps["batch"].max() <= 16
+
+
+def test_unaligned_sources_are_copied_exactly(workload):
+    """Request inputs starting at every misalignment 0..15 (the byte-wise copy path)."""
+    trace, pools, reqs = workload
+    pick = np.nonzero(trace.nbytes < (1 << 20))[0][:64]
+    r = reqs[pick].copy()
+    shift = (np.arange(len(pick)) % 16).astype(np.uint64)
+    # keep each window inside its pool: move it left when the shift would run past the end
+    room = POOL - (trace.offset[pick] + trace.nbytes[pick])
+    shift = np.where(room >= shift, shift, 0)
+    r["src"] = r["src"] + shift
+    r["arrival"] = 0.0
+    srv = S.Server(1 << 28, max_requests=64, max_batch=32, streams=2)
+    comps = srv.run_trace(r)
+    srv.close()
+    for j, i in enumerate(pick):
+        k, n = int(trace.ks[i]), int(trace.lengths[i])
+        p, o = int(trace.pool[i]), int(trace.offset[i]) + int(shift[j])
+        exp = oracle_counts(pools.host[p][o:o + n * k // 8], n, k)
+        assert comps["status"][j] == 0
+        assert (comps["counts"][j][:k].astype(np.int64) == exp).all(), f"request {i} shift {shift[j]}"
