@@ -346,16 +346,23 @@ def main():
               file=sys.stderr)
         sys.exit(3)
     print(f"[bench] {desc}: uploading {nbytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
-    dev = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    # Inputs smaller than 1 GiB would stay in the 256 MB last-level cache between
+    # steps; such workloads cycle through identical copies spanning at least 2 GiB.
+    copies = 1 if nbytes >= (1 << 30) else min(1024, -(-(2 << 30) // nbytes))
+    stride = -(-nbytes // 256) * 256
+    dev = torch.empty(stride * copies, dtype=torch.uint8, device="cuda")
     upload(dev, nbytes, dist, SEED + 2)
+    for c in range(1, copies):
+        dev[c * stride:c * stride + nbytes].copy_(dev[:nbytes])
+    views = [dev[c * stride:c * stride + nbytes] for c in range(copies)]
     counts = torch.zeros(k, dtype=torch.int64, device="cuda")
     cfg = dict(variant=args.variant, depth=args.depth, block_threads=args.block_threads,
                blocks_per_cu=args.blocks_per_cu)
     stream = torch.cuda.current_stream()
 
-    one = api.pospopcnt(dev, k, n=n, **cfg)  # one pass, for the consistency check
-    for _ in range(args.warmup):
-        api.pospopcnt(dev, k, n=n, out=counts, **cfg)
+    one = api.pospopcnt(views[0], k, n=n, **cfg)  # one pass, for the consistency check
+    for i in range(args.warmup):
+        api.pospopcnt(views[i % copies], k, n=n, out=counts, **cfg)
     torch.cuda.synchronize()
 
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
@@ -364,7 +371,7 @@ def main():
     t0 = time.perf_counter()
     ev[0].record(stream)
     for i in range(args.steps):
-        api.pospopcnt(dev, k, n=n, out=counts, **cfg)
+        api.pospopcnt(views[(args.warmup + i) % copies], k, n=n, out=counts, **cfg)
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -379,12 +386,12 @@ def main():
     ceiling = None
     if not args.no_ceiling:
         sink = torch.zeros(1, dtype=torch.int64, device="cuda")
-        for _ in range(args.warmup):
-            api.read_ceiling(dev, sink=sink, depth=args.depth)
+        for i in range(args.warmup):
+            api.read_ceiling(views[i % copies], sink=sink, depth=args.depth)
         cev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         cev[0].record(stream)
-        for _ in range(args.steps):
-            api.read_ceiling(dev, sink=sink, depth=args.depth)
+        for i in range(args.steps):
+            api.read_ceiling(views[(args.warmup + i) % copies], sink=sink, depth=args.depth)
         cev[1].record(stream)
         torch.cuda.synchronize()
         c_avg = cev[0].elapsed_time(cev[1]) / 1e3 / args.steps
@@ -397,12 +404,32 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu, sample_counts, s = cpu_baseline(k, dist, SEED + 2, args.cpu_seconds, nbytes)
-        g = api.pospopcnt(dev, k, n=s // (k // 8), **cfg).cpu().numpy()
+        g = api.pospopcnt(views[0], k, n=s // (k // 8), **cfg).cpu().numpy()
         ok_sample = bool((g == sample_counts.astype(np.int64)).all())
+
+    # Sec. 5: no branch depends on the data, so all-zero and all-one inputs must run as
+    # fast as random ones (timed on the same buffer, refilled, after the checks above).
+    data_independence = {"random_gbps": round(nbytes / avg_kernel / 1e9, 1)}
+    for name, fill in (("zeros", 0), ("ones", 255)):
+        views[0].fill_(fill)
+        scratch = torch.zeros(k, dtype=torch.int64, device="cuda")
+        for _ in range(2):
+            api.pospopcnt(views[0], k, n=n, out=scratch, **cfg)
+        dev0, dev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(3, min(args.steps, 10))
+        dev0.record(stream)
+        for _ in range(reps):
+            api.pospopcnt(views[0], k, n=n, out=scratch, **cfg)
+        dev1.record(stream)
+        torch.cuda.synchronize()
+        data_independence[f"{name}_gbps"] = round(nbytes / (dev0.elapsed_time(dev1) / 1e3 / reps) / 1e9, 1)
+        expect_each = 0 if fill == 0 else n
+        if not bool((scratch.cpu().numpy() == expect_each * (2 + reps)).all()):
+            ok_total = False
 
     batched, ok_batched = None, True
     if not args.no_batched:
-        del dev
+        del dev, views
         torch.cuda.empty_cache()
         batched, ok_batched = batched_leg(args, torch, api)
         torch.cuda.empty_cache()
@@ -430,7 +457,7 @@ def main():
         "dtype": "u16" if k == 16 else f"u{k}",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "k": k, "n_words": n,
-                   "bytes": nbytes, "offset": 0, "variant": args.variant,
+                   "bytes": nbytes, "offset": 0, "copies_cycled": copies, "variant": args.variant,
                    "depth": args.depth or None, "parallelism": "single GPU"},
         "words_per_s": round(n / (wall / args.steps), 1),
         "frac_of_hbm_peak": round(value / HBM_PEAK_GBPS, 4),
@@ -442,6 +469,7 @@ def main():
                      "min_launch_ms": round(float(per.min()) * 1e3, 4),
                      "kernel_source_sha256": src_hash},
         "ceiling": ceiling,
+        "data_independence": data_independence,
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,
