@@ -40,6 +40,9 @@ class Oracle:
         lib.ppc_oracle_csa.restype = None
         lib.ppc_oracle_hs16.argtypes = [_u8p, ctypes.c_uint64, ctypes.c_int, _u64p, _u64p]
         lib.ppc_oracle_hs16.restype = ctypes.c_int
+        lib.ppc_oracle_histogram.argtypes = [_u8p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                             _u64p]
+        lib.ppc_oracle_histogram.restype = ctypes.c_int
         self.lib = lib
         self.path = path
 
@@ -86,6 +89,19 @@ class Oracle:
         if rc < 0:
             raise ValueError(f"bad circuit size N={N}")
         return out, calls.value
+
+
+    def histogram(self, buf, n: int, id_bytes: int, bins: int, offset: int = 0,
+                  counts: np.ndarray = None) -> np.ndarray:
+        """counts[c] += #{ids == c} (c < bins); counts[bins] += #{ids >= bins}."""
+        a = np.ascontiguousarray(np.asarray(buf).view(np.uint8).reshape(-1))
+        if offset + n * id_bytes > a.size:
+            raise ValueError("ids outside the buffer")
+        out = np.zeros(bins + 1, dtype=np.uint64) if counts is None else counts
+        ptr = ctypes.cast(a.ctypes.data + offset, _u8p)
+        if self.lib.ppc_oracle_histogram(ptr, n, id_bytes, bins, out.ctypes.data_as(_u64p)) < 0:
+            raise ValueError("bad id width or bin count")
+        return out
 
 
 _default = None

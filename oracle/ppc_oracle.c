@@ -228,3 +228,20 @@ int ppc_oracle_hs16(const uint8_t* data, uint64_t n, int N, uint64_t* counts,
     if (csa_calls) *csa_calls = ctx.csa_calls;
     return 0;
 }
+
+/* ---- Histogram of categorical ids (Sec. 1, Table 1) ---- */
+
+int ppc_oracle_histogram(const uint8_t* ids, uint64_t n, int id_bytes, int bins,
+                         uint64_t* counts) {
+    if ((id_bytes != 1 && id_bytes != 2) || bins < 1 || bins > 64) return -1;
+    for (uint64_t j = 0; j < n; ++j) {
+        uint64_t id = ids[j * (uint64_t)id_bytes];
+        if (id_bytes == 2) id |= (uint64_t)ids[j * 2 + 1] << 8;
+        const uint64_t limit = PLANT(8) ? (uint64_t)bins - 1 : (uint64_t)bins;
+        if (id < limit)  /* planted: the last category treated as out of range */
+            counts[id] += 1;
+        else
+            counts[bins] += 1;
+    }
+    return 0;
+}

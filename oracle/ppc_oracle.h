@@ -55,6 +55,16 @@ void ppc_oracle_csa(uint64_t a, uint64_t b, uint64_t c, uint64_t* h, uint64_t* l
 int ppc_oracle_hs16(const uint8_t* data, uint64_t n, int N, uint64_t* counts,
                     uint64_t* csa_calls);
 
+/* Histogram of categorical ids -- the paper's motivating use (Sec. 1, Table 1):
+ * category c is bit c of a one-hot word, and the positional population count
+ * of the one-hot stream is the frequency histogram.  Computed here directly
+ * from the ids: ids are n little-endian unsigned integers of id_bytes (1 or 2)
+ * bytes each, at any alignment; counts[c] += number of ids equal to c for
+ * c < bins, and counts[bins] += number of ids >= bins (ids with no one-hot code
+ * of `bins` bits).  bins in 1..64.  Returns 0 or -1 on bad arguments. */
+int ppc_oracle_histogram(const uint8_t* ids, uint64_t n, int id_bytes, int bins,
+                         uint64_t* counts);
+
 #ifdef __cplusplus
 }
 #endif

@@ -294,3 +294,52 @@ def test_planted_mistakes_are_caught(tmp_path, plant):
     o = oracle.Oracle(lib)
     caught = [p.__name__ for p in PINS if p(o)]
     assert caught, f"planted mistake '{PLANTS[plant]}' passed every pin"
+
+
+# ------------------------------------------------------- histogram of categorical ids
+
+def pin_histogram(o):
+    """The id histogram equals encode-then-count (one-hot words through the plain
+    definition), numpy's bincount, and the Table 1 example as category ids."""
+    fails = []
+    rng = np.random.Generator(np.random.PCG64(21))
+    for id_bytes in (1, 2):
+        for bins in (1, 5, 8, 16, 32, 64):
+            n = 3001
+            ids = rng.integers(0, min(256 ** id_bytes, bins + 9), size=n).astype(
+                np.uint8 if id_bytes == 1 else np.uint16)
+            h = o.histogram(ids.view(np.uint8), n, id_bytes, bins)
+            ref = np.bincount(ids.astype(np.int64), minlength=bins + 9)
+            if not ((h[:bins] == ref[:bins]).all() and h[bins] == ref[bins:].sum()):
+                fails.append(f"bincount id_bytes={id_bytes} bins={bins}")
+            k = 8 if bins <= 8 else 16 if bins <= 16 else 32 if bins <= 32 else 64
+            wt = {8: np.uint8, 16: np.uint16, 32: np.uint32, 64: np.uint64}[k]
+            valid = ids.astype(np.int64) < bins
+            words = np.where(valid, np.left_shift(np.uint64(1), ids.astype(np.uint64)
+                                                   % np.uint64(64)), np.uint64(0)).astype(wt)
+            enc = o.count(words.view(np.uint8), n, k)
+            if not ((h[:bins] == enc[:bins]).all() and h[bins] == n - int(valid.sum())):
+                fails.append(f"encode-then-count id_bytes={id_bytes} bins={bins}")
+    rows = _golden("country_example.txt")
+    mapping = {r[1]: int(r[2], 2).bit_length() - 1 for r in rows if r[0] == "mapping"}
+    stream = next(r[1:] for r in rows if r[0] == "stream")
+    hist = {r[1]: int(r[2]) for r in rows if r[0] == "histogram"}
+    ids = np.array([mapping[c] for c in stream], np.uint8)
+    h = o.histogram(ids, len(ids), 1, 8)
+    for name, expect in hist.items():
+        if int(h[mapping[name]]) != expect:
+            fails.append(f"country {name}")
+    edge = np.array([7, 8, 9, 0], np.uint8)  # bins = 8: ids 8 and 9 have no code
+    if o.histogram(edge, 4, 1, 8).tolist() != [1, 0, 0, 0, 0, 0, 0, 1, 2]:
+        fails.append("ids at and past the bin count")
+    return fails
+
+
+def test_histogram_pin(orc):
+    fails = pin_histogram(orc)
+    assert not fails, fails
+
+
+def test_planted_histogram_boundary_is_caught(tmp_path):
+    o = oracle.Oracle(obuild.build(plant=8, out=str(tmp_path / "libplant8.so")))
+    assert pin_histogram(o)
