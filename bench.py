@@ -276,6 +276,48 @@ def serving_leg(args, torch, api):
     return report, ok
 
 
+def onehot_leg(args, torch, api):
+    """Histogram of 16 GiB of categorical ids (u8: 2^34 ids, u16: 2^33 ids, Zipf(1.1)
+    over `bins` categories with 1% ids outside them) for bins 8, 16 and 32."""
+    import oracle
+    out = {}
+    ok = True
+    nbytes = 1 << 34
+    dev = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    for id_bytes in (1, 2):
+        for bins in (8, 16, 32):
+            dist = I.Dist.ids(8 * id_bytes, bins, 1.1, 0.01)
+            upload(dev, nbytes, dist, SEED + 6)
+            n = nbytes // id_bytes
+            counts = torch.zeros(bins + 1, dtype=torch.int64, device="cuda")
+            for _ in range(args.warmup):
+                api.histogram(dev, bins, id_bytes=id_bytes, out=counts)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                api.histogram(dev, bins, id_bytes=id_bytes, out=counts)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 1e3 / args.steps
+            got = counts.cpu().numpy()
+            # a 256 MiB sample against the oracle; totals must add up to n per pass
+            sample = 1 << 28
+            host = I.generate(sample, dist, SEED + 6)
+            exp = oracle.get().histogram(host, sample // id_bytes, id_bytes, bins)
+            g = api.histogram(dev, bins, id_bytes=id_bytes, n=sample // id_bytes).cpu().numpy()
+            good = bool((g == exp.astype(np.int64)).all()) and \
+                int(got.sum()) == n * (args.warmup + args.steps)
+            ok &= good
+            out[f"u{8 * id_bytes}_bins{bins}"] = {
+                "ids": n, "gbps": round(nbytes / t / 1e9, 1),
+                "frac_of_hbm_peak": round(nbytes / t / 1e9 / HBM_PEAK_GBPS, 4),
+                "ids_per_s": round(n / t, 1), "ms": round(t * 1e3, 4), "check": good}
+    del dev
+    torch.cuda.empty_cache()
+    return out, ok
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,13 +364,15 @@ def main():
         return
 
     legs = set(args.legs.split(","))
-    if not legs <= {"single", "batched", "serving"}:
-        ap.error("--legs takes single, batched and serving")
+    if not legs <= {"single", "batched", "serving", "onehot"}:
+        ap.error("--legs takes single, batched, serving and onehot")
     args.no_batched |= "batched" not in legs
     args.no_serving |= "serving" not in legs
     if "single" not in legs:
         torch.cuda.set_device(0)
         out = {}
+        if "onehot" in legs:
+            out["onehot"] = onehot_leg(args, torch, api)[0]
         if not args.no_batched:
             out["batched"] = batched_leg(args, torch, api)[0]
         if not args.no_serving:

@@ -113,6 +113,30 @@ int ppc_read_ceiling(const void* ptr, uint64_t nbytes, uint64_t* sink, ppc_strea
                      const ppc_launch_config* config);
 
 /* ------------------------------------------------------------------------
+ * Histogram of categorical ids, through their one-hot codes.
+ *
+ * With `bins` categories, category c is bit c of a bins-bit one-hot word, and the
+ * positional population count of the one-hot encoded stream is the frequency
+ * histogram (Sec. 1, Table 1).  These calls take the ids themselves and count
+ * their one-hot codes in registers, so the encoded stream is never written.
+ *   ids    device pointer to n unsigned ids of 1 (u8) or 2 (u16) bytes,
+ *          little-endian; u16 ids must be 2-byte aligned (PPC_ERR_ALIGN).
+ *   bins   8, 16 or 32 (PPC_ERR_WIDTH otherwise).
+ *   counts device, 8-byte aligned, bins + 1 uint64 entries, added into:
+ *          counts[c] += number of ids equal to c (c < bins) and
+ *          counts[bins] += number of ids >= bins (ids without a code).
+ * Other errors and conventions as for pospopcnt.
+ * ---------------------------------------------------------------------- */
+int ppc_histogram_u8(const void* ids, uint64_t n, uint32_t bins, uint64_t* counts,
+                     ppc_stream stream);
+int ppc_histogram_u16(const void* ids, uint64_t n, uint32_t bins, uint64_t* counts,
+                      ppc_stream stream);
+/* id_bytes 1 or 2; config as for pospopcnt_ex except that depth must be 0 (the
+ * circuit spans one tile: 64 u8 or 32 u16 ids per lane).  NULL = defaults. */
+int ppc_histogram_ex(const void* ids, uint64_t n, int id_bytes, uint32_t bins, uint64_t* counts,
+                     ppc_stream stream, const ppc_launch_config* config);
+
+/* ------------------------------------------------------------------------
  * Many streams in one launch.
  *
  * A descriptor names one stream (same conventions as the single-stream calls).

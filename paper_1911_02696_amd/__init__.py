@@ -8,7 +8,7 @@ paper_1911_02696_amd.build``); there is no CPU fallback.
 from ._lib import LIB_PATH, LaunchConfig, PpcError  # noqa: F401
 
 _API = {"pospopcnt", "pospopcnt_u8", "pospopcnt_u16", "pospopcnt_u32", "pospopcnt_ptr",
-        "read_ceiling", "device_info", "launch_config", "stream_handle"}
+        "read_ceiling", "histogram", "device_info", "launch_config", "stream_handle"}
 
 
 def __getattr__(name):

@@ -79,6 +79,9 @@ SIGNATURES = {
     "ppc_plan_load": (_i32, [_vp, ctypes.c_char_p]),
     "ppc_plan_rejected": (_i32, [_vp, _vp, ctypes.POINTER(_u32)]),
     "pospopcnt_each": (_i32, [_vp, _u32, _vp]),
+    "ppc_histogram_u8": (_i32, [_vp, _u64, _u32, _vp, _vp]),
+    "ppc_histogram_u16": (_i32, [_vp, _u64, _u32, _vp, _vp]),
+    "ppc_histogram_ex": (_i32, [_vp, _u64, _i32, _u32, _vp, _vp, ctypes.POINTER(LaunchConfig)]),
 }
 
 _lock = threading.Lock()

@@ -114,6 +114,34 @@ def read_ceiling(x: torch.Tensor, nbytes: int | None = None, byte_offset: int = 
     return sink
 
 
+def histogram(ids: torch.Tensor, bins: int, id_bytes: int | None = None, n: int | None = None,
+              byte_offset: int = 0, out: torch.Tensor | None = None, stream=None,
+              **config) -> torch.Tensor:
+    """Histogram of n categorical ids (u8 or u16, little-endian) starting byte_offset
+    bytes into ids' memory, counted as the positional population count of their
+    one-hot codes.  Adds into `out` (bins + 1 int64 counters: one per category and a
+    last one for ids >= bins) and returns it.  id_bytes defaults to the tensor's
+    element size (1 or 2)."""
+    if bins not in (8, 16, 32):
+        raise ValueError("bins must be 8, 16 or 32")
+    id_bytes = id_bytes or ids.element_size()
+    if id_bytes not in (1, 2):
+        raise ValueError("ids are 1 or 2 bytes")
+    avail = _device_bytes(ids, byte_offset)
+    if n is None:
+        n = avail // id_bytes
+    if n < 0 or n * id_bytes > avail:
+        raise ValueError(f"{n} ids of {id_bytes} bytes do not fit in {avail} bytes")
+    out = _counts_tensor(out, bins + 1, ids.device)
+    cfg = launch_config(**config) if config else None
+    with torch.cuda.device(ids.device):
+        check(L.lib().ppc_histogram_ex(ids.data_ptr() + byte_offset, n, id_bytes, bins,
+                                       out.data_ptr(), stream_handle(stream),
+                                       ctypes.byref(cfg) if cfg is not None else None),
+              f"ppc_histogram(bins={bins}, n={n})")
+    return out
+
+
 def device_info() -> dict:
     info = L.DeviceInfo()
     check(L.lib().ppc_get_device_info(ctypes.byref(info)), "ppc_get_device_info")
@@ -124,5 +152,5 @@ def device_info() -> dict:
 
 
 __all__ = ["pospopcnt", "pospopcnt_u8", "pospopcnt_u16", "pospopcnt_u32", "pospopcnt_ptr",
-           "read_ceiling", "device_info", "launch_config", "stream_handle", "PpcError",
+           "read_ceiling", "histogram", "device_info", "launch_config", "stream_handle", "PpcError",
            "LaunchConfig"]

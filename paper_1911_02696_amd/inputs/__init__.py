@@ -26,7 +26,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libppc_gen.so")
 
-UNIFORM, BERNOULLI, ONEHOT = 0, 1, 2
+UNIFORM, BERNOULLI, ONEHOT, IDS = 0, 1, 2, 3
 
 # Base seed of the synthetic workloads: seed of config c is BASE_SEED + c.
 BASE_SEED = 0x19110269600
@@ -34,7 +34,8 @@ BASE_SEED = 0x19110269600
 
 class _Spec(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("key", ctypes.c_uint64),
-                ("threshold", ctypes.c_uint64), ("cdf", ctypes.c_uint64 * 65)]
+                ("threshold", ctypes.c_uint64), ("cdf", ctypes.c_uint64 * 65),
+                ("ncat", ctypes.c_int32), ("unused", ctypes.c_int32)]
 
 
 _lib = None
@@ -99,7 +100,9 @@ class Dist:
     kind: int
     p: float = 0.5
     k: int = 8
-    zipf_s: float | None = None  # ONEHOT: None means uniform categories
+    zipf_s: float | None = None  # ONEHOT, IDS: None means uniform categories
+    ncat: int = 0                # IDS: number of categories
+    p_invalid: float = 0.0       # IDS: share of ids >= ncat
 
     @staticmethod
     def uniform() -> "Dist":
@@ -115,16 +118,25 @@ class Dist:
     def onehot(k: int, zipf_s: float | None = None) -> "Dist":
         return Dist(ONEHOT, k=k, zipf_s=zipf_s)
 
+    @staticmethod
+    def ids(bits: int, ncat: int, zipf_s: float | None = None, p_invalid: float = 0.0) -> "Dist":
+        """Category indices (u8 or u16 words) over ncat categories; a p_invalid share
+        of the words are ids >= ncat."""
+        return Dist(IDS, k=bits, zipf_s=zipf_s, ncat=ncat, p_invalid=p_invalid)
+
     def spec(self, key: int) -> _Spec:
         s = _Spec()
         s.kind = self.kind
         s.k = self.k
         s.key = key
-        s.threshold = min(2**32, int(math.floor(self.p * 2.0**32)))
-        if self.kind == ONEHOT:
-            cdf = zipf_cdf(self.k, self.zipf_s) if self.zipf_s is not None else uniform_cdf(self.k)
+        p = self.p_invalid if self.kind == IDS else self.p
+        s.threshold = min(2**32, int(math.floor(p * 2.0**32)))
+        if self.kind in (ONEHOT, IDS):
+            n = self.k if self.kind == ONEHOT else self.ncat
+            cdf = zipf_cdf(n, self.zipf_s) if self.zipf_s is not None else uniform_cdf(n)
             for i, v in enumerate(cdf):
                 s.cdf[i] = int(v)
+            s.ncat = n
         return s
 
 

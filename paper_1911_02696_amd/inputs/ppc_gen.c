@@ -22,6 +22,11 @@
  *   ONEHOT    : word w (k bits, little-endian) is 1 << c, where u = high half
  *               of output w and c is the largest index with cdf[c] <= u
  *               (cdf[0] = 0 < cdf[1] <= ... <= cdf[k] = 2^32).
+ *   IDS       : word w (k = 8 or 16 bits) is the category index c itself, drawn
+ *               as for ONEHOT over ncat categories (cdf[0..ncat]); with
+ *               threshold > 0, a word whose low output half is below threshold
+ *               is instead an id >= ncat (ncat + low half mod 7): an id with no
+ *               category.
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -31,14 +36,16 @@
 
 #define GOLDEN 0x9E3779B97F4A7C15ULL
 
-enum { PPCGEN_UNIFORM = 0, PPCGEN_BERNOULLI = 1, PPCGEN_ONEHOT = 2 };
+enum { PPCGEN_UNIFORM = 0, PPCGEN_BERNOULLI = 1, PPCGEN_ONEHOT = 2, PPCGEN_IDS = 3 };
 
 typedef struct {
     int32_t kind;
-    int32_t k;           /* word bits for ONEHOT: 8, 16, 32 or 64 */
+    int32_t k;           /* word bits for ONEHOT (8, 16, 32, 64) and IDS (8, 16) */
     uint64_t key;        /* stream key, see ppcgen_key */
-    uint64_t threshold;  /* BERNOULLI */
-    uint64_t cdf[65];    /* ONEHOT */
+    uint64_t threshold;  /* BERNOULLI; IDS: share of ids without a category, scaled to 2^32 */
+    uint64_t cdf[65];    /* ONEHOT, IDS */
+    int32_t ncat;        /* IDS: number of categories (1 .. 64) */
+    int32_t unused;
 } ppcgen_spec;
 
 static inline uint64_t mix64(uint64_t z) {
@@ -64,14 +71,24 @@ static uint8_t bernoulli_byte(uint64_t key, uint64_t j, uint64_t thr) {
     return v;
 }
 
-static uint64_t onehot_word(const ppcgen_spec* s, uint64_t w) {
-    const uint64_t u = draw(s->key, w) >> 32;
-    int lo = 0, hi = s->k; /* invariant: cdf[lo] <= u < cdf[hi] */
+static int category(const ppcgen_spec* s, uint64_t x, int ncat) {
+    const uint64_t u = x >> 32;
+    int lo = 0, hi = ncat; /* invariant: cdf[lo] <= u < cdf[hi] */
     while (hi - lo > 1) {
         const int mid = (lo + hi) / 2;
         if (s->cdf[mid] <= u) lo = mid; else hi = mid;
     }
-    return (uint64_t)1 << lo;
+    return lo;
+}
+
+static uint64_t onehot_word(const ppcgen_spec* s, uint64_t w) {
+    return (uint64_t)1 << category(s, draw(s->key, w), s->k);
+}
+
+static uint64_t id_word(const ppcgen_spec* s, uint64_t w) {
+    const uint64_t x = draw(s->key, w);
+    if ((x & 0xFFFFFFFFu) < s->threshold) return (uint64_t)s->ncat + (x & 0xFFFFFFFFu) % 7;
+    return (uint64_t)category(s, x, s->ncat);
 }
 
 static void fill_range(uint8_t* out, uint64_t first, uint64_t nbytes, const ppcgen_spec* s) {
@@ -87,10 +104,12 @@ static void fill_range(uint8_t* out, uint64_t first, uint64_t nbytes, const ppcg
     case PPCGEN_BERNOULLI:
         for (; j < end; ++j) out[j - first] = bernoulli_byte(s->key, j, s->threshold);
         break;
-    case PPCGEN_ONEHOT: {
+    case PPCGEN_ONEHOT:
+    case PPCGEN_IDS: {
         const uint64_t wb = (uint64_t)(s->k / 8);
         while (j < end) {
-            const uint64_t w = j / wb, word = onehot_word(s, w);
+            const uint64_t w = j / wb;
+            const uint64_t word = s->kind == PPCGEN_ONEHOT ? onehot_word(s, w) : id_word(s, w);
             for (uint64_t b = j % wb; b < wb && j < end; ++b, ++j)
                 out[j - first] = (uint8_t)(word >> (8 * b));
         }
@@ -117,9 +136,12 @@ static void* fill_main(void* arg) {
  * threads <= 0: one per online CPU.  Returns 0, or -1 on a bad spec. */
 int ppcgen_fill(uint8_t* out, uint64_t first, uint64_t nbytes, const ppcgen_spec* spec,
                 int threads) {
-    if (spec->kind < 0 || spec->kind > 2) return -1;
+    if (spec->kind < 0 || spec->kind > 3) return -1;
     if (spec->kind == PPCGEN_ONEHOT &&
         !(spec->k == 8 || spec->k == 16 || spec->k == 32 || spec->k == 64))
+        return -1;
+    if (spec->kind == PPCGEN_IDS &&
+        (!(spec->k == 8 || spec->k == 16) || spec->ncat < 1 || spec->ncat > 64))
         return -1;
     if (threads <= 0) {
         long c = sysconf(_SC_NPROCESSORS_ONLN);

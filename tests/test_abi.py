@@ -164,3 +164,18 @@ def test_plan_needs_a_device(lib):
     h = ctypes.c_void_p()
     assert lib.ppc_plan_create(ctypes.byref(L.WorkloadHint(16, 0)), ctypes.byref(h)) == 5
     assert not h.value
+
+
+def test_histogram_arguments(lib):
+    assert lib.ppc_histogram_u8(None, 0, 8, None, None) == 0           # n = 0: no-op
+    for bins in (0, 4, 12, 64):
+        assert lib.ppc_histogram_u8(0x1000, 5, bins, 0x8000, None) == 3
+    assert lib.ppc_histogram_u8(None, 5, 8, 0x8000, None) == 1
+    assert lib.ppc_histogram_u8(0x1000, 5, 8, None, None) == 1
+    assert lib.ppc_histogram_u8(0x1000, 5, 8, 0x8004, None) == 2
+    assert lib.ppc_histogram_u16(0x1001, 5, 8, 0x8000, None) == 2      # u16 ids 2-aligned
+    assert lib.ppc_histogram_u8(0x1000, 100, 8, 0x1000 + 64, None) == 8  # counts inside ids
+    assert lib.ppc_histogram_u16(0x1000, 2**63, 8, 0x8, None) == 4
+    assert lib.ppc_histogram_ex(0x1000, 5, 3, 8, 0x8000, None, None) == 7
+    bad = L.LaunchConfig(depth=16)
+    assert lib.ppc_histogram_ex(0x1000, 5, 1, 8, 0x8000, None, ctypes.byref(bad)) == 7

@@ -1,0 +1,67 @@
+"""GPU parity of the one-hot histogram: counts of u8/u16 category ids equal the
+oracle's histogram (tolerance 0), and equal encoding the ids as one-hot words and
+counting those with pospopcnt."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1911_02696_amd import api
+from paper_1911_02696_amd import inputs as I
+
+import oracle
+from gpu_util import counts_np, say, to_device
+
+pytestmark = pytest.mark.gpu
+SEED = I.BASE_SEED + 6
+
+
+def expected(host, n, id_bytes, bins, offset=0):
+    return oracle.get().histogram(host, n, id_bytes, bins, offset=offset).astype(np.int64)
+
+
+@pytest.mark.parametrize("id_bytes", [1, 2])
+@pytest.mark.parametrize("bins", [8, 16, 32])
+def test_histogram_lengths_offsets(id_bytes, bins):
+    lengths = [0, 1, 2, 3, 7, 8, 15, 16, 17, 31, 33, 63, 64, 65, 1023, 1024, 1025,
+               4095, 4096, 4097, 16383, 16385, 100003]
+    host = I.generate(max(lengths) * id_bytes, I.Dist.ids(8 * id_bytes, bins, 1.1, 0.03), SEED)
+    for off in range(0, 16, id_bytes):
+        say(f"histogram id_bytes={id_bytes} bins={bins} offset={off}")
+        buf, o = to_device(host, off)
+        for n in lengths:
+            got = counts_np(api.histogram(buf, bins, id_bytes=id_bytes, n=n, byte_offset=o))
+            assert (got == expected(host, n, id_bytes, bins)).all(), (id_bytes, bins, off, n)
+
+
+@pytest.mark.parametrize("id_bytes", [1, 2])
+def test_histogram_equals_encode_then_count(id_bytes):
+    """The fused path equals writing the one-hot words and counting them."""
+    n = 1_000_003
+    for bins, k in ((8, 8), (16, 16), (32, 32)):
+        host = I.generate(n * id_bytes, I.Dist.ids(8 * id_bytes, bins), SEED + bins)
+        ids = torch.from_numpy(host).cuda()
+        hist = counts_np(api.histogram(ids, bins, id_bytes=id_bytes))
+        idv = host.view(np.uint8 if id_bytes == 1 else np.uint16).astype(np.uint64)
+        words = (np.uint64(1) << idv).astype({8: np.uint8, 16: np.uint16, 32: np.uint32}[k])
+        enc = counts_np(api.pospopcnt(torch.from_numpy(words.view(np.uint8)).cuda(), k))
+        assert (hist[:bins] == enc[:bins]).all() and hist[bins] == 0
+
+
+def test_histogram_all_invalid_and_configs():
+    n = 300_007
+    host = I.generate(n, I.Dist.ids(8, 8, None, 1.0), SEED + 1)  # every id >= 8
+    got = counts_np(api.histogram(torch.from_numpy(host).cuda(), 8))
+    assert (got[:8] == 0).all() and got[8] == n
+    host = I.generate(2 * n, I.Dist.ids(16, 32, 1.1, 0.1), SEED + 2)
+    exp = expected(host, n, 2, 32)
+    buf, o = to_device(host, 2)
+    for cfg in (dict(block_threads=64), dict(blocks_per_cu=1), dict(grid=3), dict(grid=1)):
+        got = counts_np(api.histogram(buf, 32, id_bytes=2, n=n, byte_offset=o, **cfg))
+        assert (got == exp).all(), cfg
+
+
+def test_country_example_as_ids():
+    ids = np.array([4, 4, 2, 4, 0, 2, 0, 0, 0, 5], np.uint8)  # France, ..., China
+    buf, o = to_device(ids, 3)
+    got = counts_np(api.histogram(buf, 8, n=10, byte_offset=o))
+    assert got.tolist() == [4, 0, 2, 0, 3, 1, 0, 0, 0]
