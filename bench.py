@@ -277,42 +277,51 @@ def serving_leg(args, torch, api):
 
 
 def onehot_leg(args, torch, api):
-    """Histogram of 16 GiB of categorical ids (u8: 2^34 ids, u16: 2^33 ids, Zipf(1.1)
-    over `bins` categories with 1% ids outside them) for bins 8, 16 and 32."""
+    """Histogram of 16 GiB of categorical ids (u8: 2^34 ids, u16: 2^33 ids) for 8, 16
+    and 32 categories.  Ids follow Zipf(1.1) over the categories, every id a category
+    as in the paper's example (Table 1); two more cases put 1% of the ids outside the
+    categories, which sends nearly every tile through the masked code path.  The first
+    GiB of each id stream is generated and repeated over the 16 GiB on the device (1 GiB
+    is far beyond the 256 MB last-level cache, so every pass still reads HBM)."""
     import oracle
     out = {}
     ok = True
-    nbytes = 1 << 34
+    nbytes, gen = 1 << 34, 1 << 30
     dev = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
-    for id_bytes in (1, 2):
-        for bins in (8, 16, 32):
-            dist = I.Dist.ids(8 * id_bytes, bins, 1.1, 0.01)
-            upload(dev, nbytes, dist, SEED + 6)
-            n = nbytes // id_bytes
-            counts = torch.zeros(bins + 1, dtype=torch.int64, device="cuda")
-            for _ in range(args.warmup):
-                api.histogram(dev, bins, id_bytes=id_bytes, out=counts)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(args.steps):
-                api.histogram(dev, bins, id_bytes=id_bytes, out=counts)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) / 1e3 / args.steps
-            got = counts.cpu().numpy()
-            # a 256 MiB sample against the oracle; totals must add up to n per pass
-            sample = 1 << 28
-            host = I.generate(sample, dist, SEED + 6)
-            exp = oracle.get().histogram(host, sample // id_bytes, id_bytes, bins)
-            g = api.histogram(dev, bins, id_bytes=id_bytes, n=sample // id_bytes).cpu().numpy()
-            good = bool((g == exp.astype(np.int64)).all()) and \
-                int(got.sum()) == n * (args.warmup + args.steps)
-            ok &= good
-            out[f"u{8 * id_bytes}_bins{bins}"] = {
-                "ids": n, "gbps": round(nbytes / t / 1e9, 1),
-                "frac_of_hbm_peak": round(nbytes / t / 1e9 / HBM_PEAK_GBPS, 4),
-                "ids_per_s": round(n / t, 1), "ms": round(t * 1e3, 4), "check": good}
+    cases = [(idb, bins, 0.0) for idb in (1, 2) for bins in (8, 16, 32)]
+    cases += [(1, 8, 0.01), (2, 16, 0.01)]
+    for id_bytes, bins, p_invalid in cases:
+        dist = I.Dist.ids(8 * id_bytes, bins, 1.1, p_invalid)
+        upload(dev, gen, dist, SEED + 6)
+        for c in range(1, nbytes // gen):
+            dev[c * gen:(c + 1) * gen].copy_(dev[:gen])
+        n = nbytes // id_bytes
+        counts = torch.zeros(bins + 1, dtype=torch.int64, device="cuda")
+        for _ in range(args.warmup):
+            api.histogram(dev, bins, id_bytes=id_bytes, out=counts)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            api.histogram(dev, bins, id_bytes=id_bytes, out=counts)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / args.steps
+        got = counts.cpu().numpy()
+        # a 256 MiB sample against the oracle; totals must add up to n per pass
+        sample = 1 << 28
+        host = I.generate(sample, dist, SEED + 6)
+        exp = oracle.get().histogram(host, sample // id_bytes, id_bytes, bins)
+        g = api.histogram(dev, bins, id_bytes=id_bytes, n=sample // id_bytes).cpu().numpy()
+        passes = args.warmup + args.steps
+        good = bool((g == exp.astype(np.int64)).all()) and int(got.sum()) == n * passes
+        ok &= good
+        name = f"u{8 * id_bytes}_bins{bins}" + ("_1pct_invalid" if p_invalid else "")
+        out[name] = {
+            "ids": n, "gbps": round(nbytes / t / 1e9, 1),
+            "frac_of_hbm_peak": round(nbytes / t / 1e9 / HBM_PEAK_GBPS, 4),
+            "ids_per_s": round(n / t, 1), "ms": round(t * 1e3, 4),
+            "invalid_ids_per_pass": int(got[bins]) // passes, "check": good}
     del dev
     torch.cuda.empty_cache()
     return out, ok
@@ -333,9 +342,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 20,000-stream batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
-    ap.add_argument("--legs", default="single,batched,serving",
-                    help="comma-separated subset of single,batched,serving to run (the JSON "
-                         "line is printed only when the single leg runs)")
+    ap.add_argument("--legs", default="single,batched,serving,onehot",
+                    help="comma-separated subset of single,batched,serving,onehot to run (the "
+                         "full JSON line is printed only when the single leg runs)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-reference", type=int, default=0, metavar="BYTES",
@@ -471,15 +480,18 @@ def main():
         if not bool((scratch.cpu().numpy() == expect_each * (2 + reps)).all()):
             ok_total = False
 
+    del dev, views
+    torch.cuda.empty_cache()
     batched, ok_batched = None, True
     if not args.no_batched:
-        del dev, views
-        torch.cuda.empty_cache()
         batched, ok_batched = batched_leg(args, torch, api)
         torch.cuda.empty_cache()
     serving, ok_serving = None, True
     if not args.no_serving:
         serving, ok_serving = serving_leg(args, torch, api)
+    onehot, ok_onehot = None, True
+    if "onehot" in legs:
+        onehot, ok_onehot = onehot_leg(args, torch, api)
 
     achieved = nbytes / avg_kernel / 1e9
     src_hash = kernel_source_hash()
@@ -516,6 +528,7 @@ def main():
         "data_independence": data_independence,
         "batched": batched,
         "serving": serving,
+        "histogram": onehot,
         "cpu_baseline": cpu,
         "check": {"total_equals_passes_times_one_pass": ok_total,
                   "sample_equals_oracle": ok_sample},
@@ -523,7 +536,7 @@ def main():
                    "clock_mhz": info["clock_khz"] / 1000},
     }
     print(json.dumps(line), flush=True)
-    if not ok_total or ok_sample is False or not ok_batched or not ok_serving:
+    if not ok_total or ok_sample is False or not ok_batched or not ok_serving or not ok_onehot:
         sys.exit(1)
 
 

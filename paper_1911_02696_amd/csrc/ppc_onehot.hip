@@ -5,12 +5,12 @@
 // c is bit c of a bins-bit one-hot word, and the positional population count of
 // the encoded stream is the frequency histogram.  Here each lane loads raw ids
 // (u8 or u16) with the same nontemporal dwordx4 tiles as the counting kernel,
-// expands every id into its one-hot dword in registers (1 << id, or nothing for
-// an id >= bins, which is tallied apart), and feeds the one-hot dwords to the
-// Harley-Seal circuit of Sec. 2: 64 u8 ids (or 32 u16 ids) per lane per tile make
-// one 64- (32-) input circuit, whose carry is counted per category class as in
-// the counting kernel.  Head and tail ids outside the 16-byte aligned body are
-// expanded one per lane by the first wave; padding never becomes an id.
+// turns them into packed one-hot codes in registers (see Codes: four 8-bit, two
+// 16-bit or one 32-bit code per dword; ids >= bins have no code and are tallied
+// apart), and feeds the code dwords of a tile to one Harley-Seal circuit of
+// Sec. 2, whose carry is counted per category class as in the counting kernel.
+// Head and tail ids outside the 16-byte aligned body are expanded one per lane by
+// the first wave; padding never becomes an id.
 #include "ppc_device.h"
 #include "ppc_internal.h"
 
@@ -18,35 +18,199 @@ namespace ppc {
 
 constexpr int kOnehotThreads = 256;
 
-// One-hot dwords of the ids in dword x (4 u8 ids or 2 u16 ids, low id first).
-// Ids >= C have no code; they add to `other`.  valid = false: x holds no ids.
+// Packed one-hot codes.  A code needs only C bits, so a 32-bit "code dword" holds
+// 32 / C codes (C = 8: four bytes, C = 16: two halves, C = 32: one dword) and the
+// circuit's class masks (mask_of<C>) merge them: class i collects bit i of every
+// code in the dword.  A tile is 16 input dwords per lane (four dwordx4 loads):
+// 16 * (4 / IDB) ids, hence NCODE = 2 C / IDB code dwords, one circuit of that
+// many inputs.
 template <int C, int IDB>
-__device__ __forceinline__ void expand(uint32_t* o, uint32_t x, uint32_t& other, bool valid) {
-#pragma unroll
-    for (int i = 0; i < 4 / IDB; ++i) {
-        const uint32_t id = IDB == 1 ? (x >> (8 * i)) & 0xFFu : (x >> (16 * i)) & 0xFFFFu;
-        const bool code = valid && id < (uint32_t)C;
-        o[i] = code ? (1u << id) : 0u;
-        other += (valid && !code) ? 1u : 0u;
+struct Codes {
+    static constexpr int IDS_PER_IN = 4 / IDB;
+    static constexpr int CODES_PER_DW = 32 / C;
+    static constexpr int NIN = 16;
+    static constexpr int NCODE = NIN * IDS_PER_IN / CODES_PER_DW;
+    static constexpr int LOGC = C == 8 ? 3 : C == 16 ? 4 : 5;
+    static constexpr uint32_t LANE = IDB == 1 ? 0x01010101u : 0x00010001u;  // 1 per id lane
+    static constexpr uint32_t IDMASK = IDB == 1 ? 0xFFu : 0xFFFFu;
+    // Input bits that are zero in every input dword whose ids are all < C.
+    static constexpr uint32_t BAD = LANE * (IDMASK & ~(uint32_t)(C - 1));
+
+    // Lanes of ids >= C, all ones per such id; *count receives how many there are.
+    // Per lane the high id bits, moved down, are at most 31 (bytes) or 0x1FFF
+    // (halves), so adding 0x7F / 0x7FFF sets the lane's top bit exactly for a
+    // nonzero value and never carries into the next lane.
+    __device__ static __forceinline__ uint32_t dead_ids(uint32_t x, uint32_t* count) {
+        const uint32_t top = IDB == 1 ? 0x80808080u : 0x80008000u;
+        const uint32_t z = (((x & BAD) >> LOGC) + (top - LANE)) & top;
+        *count = __builtin_popcount(z);
+        return z | (z - (z >> (IDB == 1 ? 7 : 15)));
     }
+
+    // Code dwords of NIN input dwords; dead[i] marks ids of in[i] that get no code.
+    // C = 8: one byte-table lookup per four codes (v_perm_b32: byte b of the result
+    // is byte sel_b of {S0:S1}; the table {0x80402010 : 0x08040201} holds 1 << j at
+    // byte j, and selector 0x0C yields zero, which is what a dead id is mapped to).
+    // C = 16: packed 16-bit shifts, two codes per op, dead halves masked.  C = 32:
+    // one byte- or word-selecting shift per id, dead ids masked.
+    __device__ static __forceinline__ void make(uint32_t* code, const uint32_t* in,
+                                                const uint32_t* dead) {
+        // Dead ids are zeroed first, so that every shift amount below is in range;
+        // the code each of them then gets is cleared again.
+        uint32_t live[NIN];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) live[i] = in[i] & ~dead[i];
+        if constexpr (C == 8) {
+            if constexpr (IDB == 1) {
+#pragma unroll
+                for (int i = 0; i < NIN; ++i)
+                    code[i] = __builtin_amdgcn_perm(0x80402010u, 0x08040201u,
+                                                    live[i] | (dead[i] & 0x0C0C0C0Cu));
+            } else {
+#pragma unroll
+                for (int i = 0; i < NIN / 2; ++i) {
+                    const uint32_t lo = live[2 * i] | (dead[2 * i] & 0x000C000Cu);
+                    const uint32_t hi = live[2 * i + 1] | (dead[2 * i + 1] & 0x000C000Cu);
+                    // the four id bytes, then the table lookup
+                    const uint32_t sel = __builtin_amdgcn_perm(hi, lo, 0x06040200u);
+                    code[i] = __builtin_amdgcn_perm(0x80402010u, 0x08040201u, sel);
+                }
+            }
+        } else if constexpr (C == 16) {
+            typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+            const u16x2 one = {1, 1};
+            if constexpr (IDB == 1) {
+#pragma unroll
+                for (int i = 0; i < NIN; ++i) {
+                    // ids 0 and 1 (2 and 3) widened to the two 16-bit shift amounts
+                    const uint32_t a = __builtin_amdgcn_perm(0u, live[i], 0x0C010C00u);
+                    const uint32_t b = __builtin_amdgcn_perm(0u, live[i], 0x0C030C02u);
+                    const uint32_t da = __builtin_amdgcn_perm(0u, dead[i], 0x01010000u);
+                    const uint32_t db = __builtin_amdgcn_perm(0u, dead[i], 0x03030202u);
+                    code[2 * i] =
+                        __builtin_bit_cast(uint32_t, one << __builtin_bit_cast(u16x2, a)) & ~da;
+                    code[2 * i + 1] =
+                        __builtin_bit_cast(uint32_t, one << __builtin_bit_cast(u16x2, b)) & ~db;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < NIN; ++i)
+                    code[i] = __builtin_bit_cast(uint32_t, one << __builtin_bit_cast(u16x2, live[i])) &
+                              ~dead[i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) {
+#pragma unroll
+                for (int j = 0; j < IDS_PER_IN; ++j) {
+                    const int sh = 32 / IDS_PER_IN * j;
+                    const uint32_t keep =
+                        ~(uint32_t)__builtin_amdgcn_sbfe((int)dead[i], sh, 32 / IDS_PER_IN);
+                    code[i * IDS_PER_IN + j] = (1u << ((live[i] >> sh) & IDMASK)) & keep;
+                }
+            }
+        }
+    }
+};
+
+template <int C, int IDB, int LOGD>
+__device__ __forceinline__ uint32_t onehot_step(uint32_t (&B)[LOGD], uint32_t& other,
+                                                const u32x4 (&v)[4],
+                                            const bool (&valid)[4], bool maybe_partial) {
+    using K = Codes<C, IDB>;
+    static_assert(K::NCODE == (1 << LOGD), "one circuit per tile");
+    uint32_t in[K::NIN];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        in[4 * j + 0] = v[j].x;
+        in[4 * j + 1] = v[j].y;
+        in[4 * j + 2] = v[j].z;
+        in[4 * j + 3] = v[j].w;
+    }
+    uint32_t any = 0;
+#pragma unroll
+    for (int i = 0; i < K::NIN; ++i) any |= in[i];
+    const uint32_t bad = any & K::BAD;
+    uint32_t code[K::NCODE], dead[K::NIN];
+    // Wave-uniform choice: ids are masked only when some lane holds an id >= C or
+    // the tile is the partial last one (whose missing units carry no ids at all).
+    if (!maybe_partial && __ballot(bad != 0) == 0) {
+#pragma unroll
+        for (int i = 0; i < K::NIN; ++i) dead[i] = 0;
+    } else {
+#pragma unroll
+        for (int i = 0; i < K::NIN; ++i) {
+            uint32_t n = 0;
+            const uint32_t d = K::dead_ids(in[i], &n);
+            const bool unit = valid[i / 4];
+            dead[i] = unit ? d : 0xFFFFFFFFu;
+            other += unit ? n : 0u;
+        }
+    }
+    K::make(code, in, dead);
+    return Circuit<LOGD>::run(B, code);
 }
 
-template <int C, int IDB, int U, int LOGD>
-__device__ __forceinline__ void onehot_step(uint32_t (&B)[LOGD], uint32_t (&cnt)[C],
-                                            uint32_t& other, const u32x4 (&v)[U],
-                                            const bool (&valid)[U]) {
-    constexpr int PER = 4 / IDB;
-    static_assert(4 * U * PER == (1 << LOGD), "one circuit per tile");
-    uint32_t d[4 * U * PER];
+// The Harley-Seal recursion of Sec. 2 carried on past the tile: F_{N+1} is two F_N
+// and one CSA, so the carries of successive tile circuits (weight 2^LOGD each)
+// enter E more levels.  Level e keeps a running plane R[e] and one pending carry
+// P[e] of weight 2^(LOGD + e); the second carry to reach a level is merged with
+// the pending one and R[e] by a CSA whose carry moves up a level.  Only carries
+// leaving the top level are counted per class (Sec. 4.1), once every 2^E tiles.
+// The tile number is the same in every lane, so the level choice is a scalar
+// branch.
+template <int C, int LOGD, int E>
+struct TileTree {
+    uint32_t R[E], P[E], cnt[C];
+    uint32_t tiles;
+
+    __device__ __forceinline__ void init() {
 #pragma unroll
-    for (int j = 0; j < U; ++j) {
-        expand<C, IDB>(d + (4 * j + 0) * PER, v[j].x, other, valid[j]);
-        expand<C, IDB>(d + (4 * j + 1) * PER, v[j].y, other, valid[j]);
-        expand<C, IDB>(d + (4 * j + 2) * PER, v[j].z, other, valid[j]);
-        expand<C, IDB>(d + (4 * j + 3) * PER, v[j].w, other, valid[j]);
+        for (int e = 0; e < E; ++e) R[e] = P[e] = 0;
+#pragma unroll
+        for (int i = 0; i < C; ++i) cnt[i] = 0;
+        tiles = 0;
     }
-    count_classes<C>(cnt, Circuit<LOGD>::run(B, d));
-}
+
+    __device__ __forceinline__ void add(uint32_t c) {
+        bool up = true;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (up) {
+                if (((tiles >> e) & 1u) == 0) {
+                    P[e] = c;
+                    up = false;
+                } else {
+                    uint32_t h, l;
+                    csa(h, l, R[e], P[e], c);
+                    R[e] = l;
+                    P[e] = 0;
+                    c = h;
+                }
+            }
+        }
+        if (up) count_classes<C>(cnt, c);
+        ++tiles;
+    }
+
+    // Per-lane class totals: counted carries have weight 2^(LOGD + E), level e's
+    // planes 2^(LOGD + e), the tile circuit's running planes B[j] 2^j; e0 is a
+    // dword counted with weight 1.
+    __device__ __forceinline__ void totals(uint32_t (&out)[C], const uint32_t (&B)[LOGD],
+                                           uint32_t e0) const {
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const uint32_t m = mask_of<C>(i);
+            uint32_t t = (cnt[i] << (LOGD + E)) + __builtin_popcount(e0 & m);
+#pragma unroll
+            for (int j = 0; j < LOGD; ++j) t += __builtin_popcount(B[j] & m) << j;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                t += (__builtin_popcount(R[e] & m) + __builtin_popcount(P[e] & m)) << (LOGD + e);
+            out[i] = t;
+        }
+    }
+};
 
 // The id at head or tail position `lane` of the first wave: lanes 0..15 take
 // head ids, lanes 16..31 tail ids.  u16 ids are 2-byte aligned, so the head and
@@ -71,7 +235,8 @@ __global__ void __launch_bounds__(kOnehotThreads)
 onehot_kernel(const u32x4* __restrict__ body, uint64_t units, Edges edges,
               unsigned long long* __restrict__ counts) {
     constexpr int U = 4;
-    constexpr int LOGD = IDB == 1 ? 6 : 5;  // 64 u8 or 32 u16 ids per lane per tile
+    constexpr int LOGD = C == 8 ? (IDB == 1 ? 4 : 3) : C == 16 ? (IDB == 1 ? 5 : 4)
+                                                                : (IDB == 1 ? 6 : 5);
     constexpr uint64_t TILE = (uint64_t)kWave * U;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
@@ -80,14 +245,16 @@ onehot_kernel(const u32x4* __restrict__ body, uint64_t units, Edges edges,
     const uint64_t nw = (uint64_t)gridDim.x * wpb;
     const uint64_t full = units / TILE;
 
-    uint32_t B[LOGD], cnt[C], other = 0;
+    // Levels past the tile: more for wider codes, whose per-class count costs more.
+    constexpr int E = C == 8 ? 1 : C == 16 ? 2 : 3;
+    uint32_t B[LOGD], other = 0;
 #pragma unroll
     for (int j = 0; j < LOGD; ++j) B[j] = 0;
-#pragma unroll
-    for (int i = 0; i < C; ++i) cnt[i] = 0;
+    TileTree<C, LOGD, E> tree;
+    tree.init();
     const bool all[U] = {true, true, true, true};
     walk_tiles<U>(body, full, gw, nw, lane, [&](const u32x4(&v)[U]) {
-        onehot_step<C, IDB, U, LOGD>(B, cnt, other, v, all);
+        tree.add(onehot_step<C, IDB, LOGD>(B, other, v, all, false));
     });
     const uint64_t rem = units - full * TILE;
     if (rem != 0 && gw == full % nw) {
@@ -96,12 +263,12 @@ onehot_kernel(const u32x4* __restrict__ body, uint64_t units, Edges edges,
         bool valid[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) valid[j] = (uint64_t)(j * kWave + lane) < rem;
-        onehot_step<C, IDB, U, LOGD>(B, cnt, other, t, valid);
+        tree.add(onehot_step<C, IDB, LOGD>(B, other, t, valid, true));
     }
     const uint32_t e = (blockIdx.x == 0 && wave == 0) ? edge_onehot<C, IDB>(edges, lane, other) : 0u;
 
     uint32_t tot[C];
-    lane_totals<C, LOGD>(tot, cnt, B, e);
+    tree.totals(tot, B, e);
     const uint32_t v = wave_reduce_scatter<C>(tot, lane);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) other += (uint32_t)__shfl_xor((int)other, o, kWave);
@@ -129,6 +296,21 @@ static const void* onehot_of(int bins, int id_bytes) {
     return (const void*)table[id_bytes - 1][bins == 8 ? 0 : bins == 16 ? 1 : 2];
 }
 
+// Default launch shape per (categories, id width), the fastest of a sweep of block
+// sizes 64..256 and 1..12 blocks per CU over 16 GiB of ids on MI355X.  All of them
+// keep more waves resident than the counting kernel: each id costs an expansion on
+// top of its share of the circuit, so there is more arithmetic to overlap with the
+// loads, most of all for 32 categories of u8 ids (one 32-bit code per id).
+struct OnehotShape {
+    int threads, blocks_per_cu;
+};
+
+static OnehotShape onehot_shape(int bins, int id_bytes) {
+    if (id_bytes == 1) return bins == 8 ? OnehotShape{256, 2} : bins == 16 ? OnehotShape{64, 8}
+                                                                           : OnehotShape{256, 8};
+    return bins == 32 ? OnehotShape{64, 6} : OnehotShape{256, 2};
+}
+
 static int launch_histogram(const void* ids, uint64_t n, int id_bytes, int bins,
                             uint64_t* counts, ppc_stream stream, const ppc_launch_config* cfg) {
     if (id_bytes != 1 && id_bytes != 2) return PPC_ERR_ARG;
@@ -146,7 +328,8 @@ static int launch_histogram(const void* ids, uint64_t n, int id_bytes, int bins,
     ppc_launch_config c = {};
     if (cfg) c = *cfg;
     if (c.variant != PPC_VARIANT_CSA || (c.depth != 0)) return PPC_ERR_ARG;
-    const int threads = c.block_threads ? c.block_threads : kOnehotThreads;
+    const OnehotShape dflt = onehot_shape(bins, id_bytes);
+    const int threads = c.block_threads ? c.block_threads : dflt.threads;
     if (threads < kWave || threads > kOnehotThreads || threads % kWave) return PPC_ERR_ARG;
     if (c.blocks_per_cu < 0 || c.grid < 0) return PPC_ERR_ARG;
     const DeviceFacts* dev = nullptr;
@@ -161,10 +344,7 @@ static int launch_histogram(const void* ids, uint64_t n, int id_bytes, int bins,
     if (c.grid > 0) {
         grid = c.grid;
     } else {
-        // More resident waves than the counting kernel: each id costs an
-        // expansion on top of its share of the circuit, so there is more
-        // arithmetic to overlap with the loads.
-        const int bpc = c.blocks_per_cu ? c.blocks_per_cu : 2;
+        const int bpc = c.blocks_per_cu ? c.blocks_per_cu : dflt.blocks_per_cu;
         grid = (int64_t)bpc * dev->cus;
         if ((uint64_t)grid > need) grid = (int64_t)need;
     }

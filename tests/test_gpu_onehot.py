@@ -65,3 +65,28 @@ def test_country_example_as_ids():
     buf, o = to_device(ids, 3)
     got = counts_np(api.histogram(buf, 8, n=10, byte_offset=o))
     assert got.tolist() == [4, 0, 2, 0, 3, 1, 0, 0, 0]
+
+
+@pytest.mark.parametrize("id_bytes", [1, 2])
+@pytest.mark.parametrize("bins", [8, 16, 32])
+def test_histogram_rare_wide_invalid(id_bytes, bins):
+    """Rare ids drawn over the whole id range (every high bit pattern, 0xFF and 0xFFFF
+    included) among valid ones: some tiles hold none, some one or a few, so tiles take
+    both the all-valid and the masked code paths within one launch."""
+    n = 2_000_003
+    dt = np.uint8 if id_bytes == 1 else np.uint16
+    ids = I.generate(n * id_bytes, I.Dist.ids(8 * id_bytes, bins, 1.1), SEED + 10 + bins).view(dt)
+    wide = I.generate(n * id_bytes, I.Dist.uniform(), SEED + 20 + bins).view(dt)
+    pick = I.generate(2 * n, I.Dist.uniform(), SEED + 30 + bins).view(np.uint16) < 3
+    ids = np.where(pick, wide, ids).astype(dt)
+    ids[[5, n // 2, n - 1]] = np.array([0xFF, 0x80, bins], np.uint64).astype(dt)
+    if id_bytes == 2:
+        ids[[7, n // 3]] = [0xFFFF, 0x8000 | 3]
+    host = ids.view(np.uint8)
+    say(f"histogram rare wide invalid id_bytes={id_bytes} bins={bins} invalid={int((ids >= bins).sum())}")
+    exp = expected(host, n, id_bytes, bins)
+    assert 0 < exp[bins] < n // 1000
+    for off in (0, 2, 6):
+        buf, o = to_device(host, off)
+        got = counts_np(api.histogram(buf, bins, id_bytes=id_bytes, n=n, byte_offset=o))
+        assert (got == exp).all(), (id_bytes, bins, off)
