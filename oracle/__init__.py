@@ -43,6 +43,9 @@ class Oracle:
         lib.ppc_oracle_histogram.argtypes = [_u8p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                              _u64p]
         lib.ppc_oracle_histogram.restype = ctypes.c_int
+        lib.ppc_oracle_count_planes.argtypes = [ctypes.POINTER(_u8p), ctypes.c_int,
+                                                ctypes.c_uint64, _u64p]
+        lib.ppc_oracle_count_planes.restype = ctypes.c_int
         self.lib = lib
         self.path = path
 
@@ -101,6 +104,23 @@ class Oracle:
         ptr = ctypes.cast(a.ctypes.data + offset, _u8p)
         if self.lib.ppc_oracle_histogram(ptr, n, id_bytes, bins, out.ctypes.data_as(_u64p)) < 0:
             raise ValueError("bad id width or bin count")
+        return out
+
+    def count_planes(self, planes, n: int, offsets=None, counts: np.ndarray = None) -> np.ndarray:
+        """Words of 16*m bits held as m planes of n uint16 limbs (plane j = limb j):
+        counts[16j + p] += #{words whose limb j has bit p set}.  planes: m byte buffers;
+        plane j starts offsets[j] bytes into planes[j]."""
+        m = len(planes)
+        offsets = [0] * m if offsets is None else list(offsets)
+        bufs = [np.ascontiguousarray(np.asarray(b).view(np.uint8).reshape(-1)) for b in planes]
+        for b, o in zip(bufs, offsets):
+            if o + 2 * n > b.size:
+                raise ValueError("plane shorter than n limbs")
+        ptrs = (_u8p * max(m, 1))(*[ctypes.cast(b.ctypes.data + o, _u8p)
+                                    for b, o in zip(bufs, offsets)])
+        out = np.zeros(16 * m, dtype=np.uint64) if counts is None else counts
+        if self.lib.ppc_oracle_count_planes(ptrs, m, n, out.ctypes.data_as(_u64p)) < 0:
+            raise ValueError("plane count must be 1..64")
         return out
 
 

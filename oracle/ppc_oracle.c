@@ -15,7 +15,8 @@
  *     2^(N-1)-input circuits plus one CSA, 2^N - 1 CSAs in all);
  *   - the counting of the carry register, the deferred weight and the final
  *     flush of the running registers: Sec. 4.1 and Fig. 6;
- *   - the scalar residual: end of Sec. 4.1.
+ *   - the scalar residual: end of Sec. 4.1;
+ *   - wider words as several 16-bit streams: Sec. 4, opening paragraph.
  *
  * Mutation hooks: building with -DPPC_ORACLE_PLANT=<id> plants one known
  * mistake (used only by the test that shows the pins catch such mistakes).
@@ -242,6 +243,18 @@ int ppc_oracle_histogram(const uint8_t* ids, uint64_t n, int id_bytes, int bins,
             counts[id] += 1;
         else
             counts[bins] += 1;
+    }
+    return 0;
+}
+
+/* ---- Wider words held as 16-bit planes (Sec. 4) ---- */
+
+int ppc_oracle_count_planes(const uint8_t* const* planes, int m, uint64_t n, uint64_t* counts) {
+    if (m < 1 || m > 64) return -1;
+    for (int j = 0; j < m; ++j) {
+        /* limb j of every word counts toward word bits 16j .. 16j+15 */
+        const int first = PLANT(9) ? 16 * (m - 1 - j) : 16 * j; /* planted: planes reversed */
+        if (ppc_oracle_count(planes[j], n, 16, counts + first) != 0) return -1;
     }
     return 0;
 }

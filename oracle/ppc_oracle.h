@@ -65,6 +65,13 @@ int ppc_oracle_hs16(const uint8_t* data, uint64_t n, int N, uint64_t* counts,
 int ppc_oracle_histogram(const uint8_t* ids, uint64_t n, int id_bytes, int bins,
                          uint64_t* counts);
 
+/* Wider words as several streams of 16-bit words (Sec. 4): a word of k = 16*m
+ * bits is held as m planes, plane j holding its 16-bit limb j (word bits 16j ..
+ * 16j+15) as n little-endian uint16 words at any alignment.  counts[16j + p] +=
+ * number of words whose limb j has bit p set, which is the count of word bit
+ * 16j + p.  planes: m host pointers.  m in 1..64.  Returns 0 or -1 on a bad m. */
+int ppc_oracle_count_planes(const uint8_t* const* planes, int m, uint64_t n, uint64_t* counts);
+
 #ifdef __cplusplus
 }
 #endif

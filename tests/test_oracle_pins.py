@@ -343,3 +343,45 @@ def test_histogram_pin(orc):
 def test_planted_histogram_boundary_is_caught(tmp_path):
     o = oracle.Oracle(obuild.build(plant=8, out=str(tmp_path / "libplant8.so")))
     assert pin_histogram(o)
+
+
+# ------------------------------------------ wider words as 16-bit planes (Sec. 4)
+
+def pin_planes(o):
+    """Words of 16*m bits held as m planes of 16-bit limbs count like the words
+    themselves: against the plain definition for k = 16, 32, 64 (the interleaved
+    words through count), and brute force on the assembled bits for m = 3, 5 and 64."""
+    fails = []
+    rng = np.random.Generator(np.random.PCG64(31))
+    for m in (1, 2, 4):
+        k = 16 * m
+        for n in (0, 1, 5, 1000):
+            words = rng.integers(0, 256, size=n * 2 * m, dtype=np.uint8)
+            limbs = words.view(np.uint16).reshape(n, m)
+            planes = [np.ascontiguousarray(limbs[:, j]) for j in range(m)]
+            if not (o.count_planes(planes, n) == o.count(words, n, k)).all():
+                fails.append(f"planes m={m} n={n} vs k={k} words")
+    for m, n in ((3, 777), (5, 300), (64, 20)):
+        limbs = rng.integers(0, 1 << 16, size=(n, m), dtype=np.uint16)
+        # planes at odd byte offsets inside larger buffers
+        bufs, offs = [], []
+        for j in range(m):
+            b = np.zeros(2 * n + 3, np.uint8)
+            b[1:1 + 2 * n] = np.ascontiguousarray(limbs[:, j]).view(np.uint8)
+            bufs.append(b)
+            offs.append(1)
+        bits = np.unpackbits(np.ascontiguousarray(limbs).view(np.uint8).reshape(n, 2 * m),
+                             axis=1, bitorder="little")
+        if not (o.count_planes(bufs, n, offsets=offs) == bits.sum(axis=0)).all():
+            fails.append(f"planes m={m} brute force")
+    return fails
+
+
+def test_planes_pin(orc):
+    fails = pin_planes(orc)
+    assert not fails, fails
+
+
+def test_planted_plane_order_is_caught(tmp_path):
+    o = oracle.Oracle(obuild.build(plant=9, out=str(tmp_path / "libplant9.so")))
+    assert pin_planes(o)
