@@ -42,7 +42,7 @@ enum {
     PPC_OK = 0,
     PPC_ERR_NULL = 1,     /* a required pointer is NULL (input or counts with n > 0) */
     PPC_ERR_ALIGN = 2,    /* counts (or a descriptor array) not 8-byte aligned */
-    PPC_ERR_WIDTH = 3,    /* k is not 8, 16 or 32 */
+    PPC_ERR_WIDTH = 3,    /* k is not 8, 16, 32 or 64 (8, 16 or 32 in batches and serving) */
     PPC_ERR_RANGE = 4,    /* n * k / 8 does not fit in 64 bits */
     PPC_ERR_HIP = 5,      /* a HIP runtime call failed: see ppc_last_hip_error() */
     PPC_ERR_BUDGET = 6,   /* serving: request larger than the memory budget */
@@ -61,7 +61,7 @@ int ppc_last_hip_error(void);
 /* ------------------------------------------------------------------------
  * Single stream.
  *
- * pospopcnt_u8 / _u16 / _u32: counts has 8 / 16 / 32 entries.
+ * pospopcnt_u8 / _u16 / _u32 / _u64: counts has 8 / 16 / 32 / 64 entries.
  *   ptr    device pointer to n*k/8 bytes, any alignment; may be NULL if n = 0.
  *   n      number of k-bit words (64-bit: inputs of 2^32 words and more are
  *          allowed, unlike the paper's uint32_t length, Fig. 3).
@@ -71,13 +71,16 @@ int ppc_last_hip_error(void);
  * Errors: PPC_ERR_NULL, PPC_ERR_ALIGN, PPC_ERR_RANGE, PPC_ERR_OVERLAP,
  * PPC_ERR_HIP (launch failure).  Nothing is launched on error.
  * The work is the Harley-Seal carry-save-adder method of Sec. 4.1 (circuits of
- * Sec. 2), with the carry counted per bit position as in Fig. 6.
+ * Sec. 2), with the carry counted per bit position as in Fig. 6.  64-bit words
+ * are the generalisation to wider words named at the start of Sec. 4: two
+ * circuits per lane, one for the low and one for the high halves.
  * ---------------------------------------------------------------------- */
 int pospopcnt_u8(const void* ptr, uint64_t n, uint64_t* counts, ppc_stream stream);
 int pospopcnt_u16(const void* ptr, uint64_t n, uint64_t* counts, ppc_stream stream);
 int pospopcnt_u32(const void* ptr, uint64_t n, uint64_t* counts, ppc_stream stream);
+int pospopcnt_u64(const void* ptr, uint64_t n, uint64_t* counts, ppc_stream stream);
 
-/* Same, with the width k in {8, 16, 32} as an argument (PPC_ERR_WIDTH otherwise). */
+/* Same, with the width k in {8, 16, 32, 64} as an argument (PPC_ERR_WIDTH otherwise). */
 int pospopcnt(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stream stream);
 
 /* Kernel variants. */
@@ -89,11 +92,11 @@ enum {
 /* Launch configuration for pospopcnt_ex.  Zero in any field selects the
  * library's default for that field. */
 typedef struct {
-    int32_t variant;        /* PPC_VARIANT_CSA or PPC_VARIANT_BALLOT */
+    int32_t variant;        /* PPC_VARIANT_CSA or PPC_VARIANT_BALLOT (k <= 32 only) */
     int32_t depth;          /* CSA: inputs per lane per circuit, 8, 16 or 32 dwords
                                (the 2^N-input circuits of Sec. 2; the paper's 256 B /
                                512 B / 1 kB circuits are N = 2, 3, 4) */
-    int32_t block_threads;  /* 64 .. 1024, multiple of 64 */
+    int32_t block_threads;  /* 64 .. 256, multiple of 64 */
     int32_t blocks_per_cu;  /* resident blocks per compute unit used to size the grid */
     int64_t grid;           /* explicit number of blocks (overrides blocks_per_cu) */
 } ppc_launch_config;
@@ -103,6 +106,29 @@ typedef struct {
  * Every configuration gives the same counts. */
 int pospopcnt_ex(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stream stream,
                  const ppc_launch_config* config);
+
+/* ------------------------------------------------------------------------
+ * Wider words as several streams of 16-bit words (Sec. 4: a word of k = 16*m
+ * bits held as m planes, plane j holding every word's 16-bit limb j, i.e. word
+ * bits 16j .. 16j+15).
+ *   planes host array of m device pointers, plane j pointing at n little-endian
+ *          uint16 limbs, any alignment; the array is read during the call only.
+ *   m      1 .. PPC_MAX_PLANES (PPC_ERR_ARG otherwise): k = 16m up to 512 bits.
+ *   n      words (limbs per plane); all planes hold n.
+ *   counts device, 8-byte aligned, 16*m uint64 entries, added into:
+ *          counts[16j + p] += number of words whose bit 16j + p is set.  Must not
+ *          overlap any plane.
+ * One launch counts every plane (the chip's blocks are shared out over them).
+ * Errors: PPC_ERR_NULL (planes, a plane or counts NULL with n > 0),
+ * PPC_ERR_ALIGN, PPC_ERR_RANGE, PPC_ERR_OVERLAP, PPC_ERR_ARG, PPC_ERR_HIP.
+ * pospopcnt_planes16_ex takes a launch configuration as pospopcnt_ex does (CSA
+ * only; blocks_per_cu and grid count blocks per plane row of the grid).
+ * ---------------------------------------------------------------------- */
+#define PPC_MAX_PLANES 32
+int pospopcnt_planes16(const void* const* planes, uint32_t m, uint64_t n, uint64_t* counts,
+                       ppc_stream stream);
+int pospopcnt_planes16_ex(const void* const* planes, uint32_t m, uint64_t n, uint64_t* counts,
+                          ppc_stream stream, const ppc_launch_config* config);
 
 /* Read-only bandwidth reference: reads the nbytes at ptr (any alignment) with
  * the same loads, tiling and grid as the CSA kernel, XOR-reduces them, and

@@ -59,12 +59,18 @@ _vp, _u64, _i32, _i64 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c
 _u32 = ctypes.c_uint32
 
 # name -> (restype, argtypes); every entry point the binding uses.
+MAX_PLANES = 32  # PPC_MAX_PLANES
+
 SIGNATURES = {
     "ppc_status_string": (ctypes.c_char_p, [_i32]),
     "ppc_last_hip_error": (_i32, []),
     "pospopcnt_u8": (_i32, [_vp, _u64, _vp, _vp]),
     "pospopcnt_u16": (_i32, [_vp, _u64, _vp, _vp]),
     "pospopcnt_u32": (_i32, [_vp, _u64, _vp, _vp]),
+    "pospopcnt_u64": (_i32, [_vp, _u64, _vp, _vp]),
+    "pospopcnt_planes16": (_i32, [ctypes.POINTER(_vp), _u32, _u64, _vp, _vp]),
+    "pospopcnt_planes16_ex": (_i32, [ctypes.POINTER(_vp), _u32, _u64, _vp, _vp,
+                                     ctypes.POINTER(LaunchConfig)]),
     "pospopcnt": (_i32, [_vp, _u64, _i32, _vp, _vp]),
     "pospopcnt_ex": (_i32, [_vp, _u64, _i32, _vp, _vp, ctypes.POINTER(LaunchConfig)]),
     "ppc_read_ceiling": (_i32, [_vp, _u64, _vp, _vp, ctypes.POINTER(LaunchConfig)]),

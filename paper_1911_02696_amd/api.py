@@ -69,8 +69,8 @@ def pospopcnt(x: torch.Tensor, k: int, n: int | None = None, byte_offset: int = 
     Adds into `out` (k int64 counters on x's device; zeros when None) and returns it.
     Keyword arguments select a launch configuration (variant='csa'|'ballot', depth,
     block_threads, blocks_per_cu, grid); every configuration gives the same counts."""
-    if k not in (8, 16, 32):
-        raise ValueError("k must be 8, 16 or 32")
+    if k not in (8, 16, 32, 64):
+        raise ValueError("k must be 8, 16, 32 or 64")
     avail = _device_bytes(x, byte_offset)
     if n is None:
         n = avail // (k // 8)
@@ -93,6 +93,47 @@ def pospopcnt_u16(x, n=None, byte_offset=0, out=None, stream=None):
 
 def pospopcnt_u32(x, n=None, byte_offset=0, out=None, stream=None):
     return pospopcnt(x, 32, n, byte_offset, out, stream)
+
+
+def pospopcnt_u64(x, n=None, byte_offset=0, out=None, stream=None):
+    return pospopcnt(x, 64, n, byte_offset, out, stream)
+
+
+def pospopcnt_planes(planes, n: int | None = None, byte_offsets=None,
+                     out: torch.Tensor | None = None, stream=None, **config) -> torch.Tensor:
+    """Positional population count of words of 16*m bits held as m planes of 16-bit
+    limbs (plane j holds every word's bits 16j .. 16j+15; the encoding of wider words
+    as several 16-bit streams, Sec. 4).
+
+    planes: a sequence of m GPU tensors (any dtype, read as bytes from byte_offsets[j])
+    or a 2-D tensor whose m rows are the planes.  n defaults to the shortest plane's
+    limb count.  Adds into `out` (16*m int64 counters) and returns it; out[16j + p]
+    counts the words whose bit 16j + p is set."""
+    if isinstance(planes, torch.Tensor):
+        if planes.dim() != 2:
+            raise ValueError("a tensor of planes must be 2-D (m rows)")
+        planes = list(planes.unbind(0))
+    planes = list(planes)
+    m = len(planes)
+    if not 1 <= m <= L.MAX_PLANES:
+        raise ValueError(f"1 to {L.MAX_PLANES} planes")
+    offs = [0] * m if byte_offsets is None else list(byte_offsets)
+    avail = [_device_bytes(p, o) for p, o in zip(planes, offs)]
+    if n is None:
+        n = min(avail) // 2
+    if n < 0 or any(2 * n > a for a in avail):
+        raise ValueError(f"{n} limbs do not fit in every plane")
+    dev = planes[0].device
+    if any(p.device != dev for p in planes):
+        raise ValueError("planes must be on one device")
+    out = _counts_tensor(out, 16 * m, dev)
+    ptrs = (ctypes.c_void_p * m)(*[p.data_ptr() + o for p, o in zip(planes, offs)])
+    cfg = launch_config(**config) if config else None
+    with torch.cuda.device(dev):
+        check(L.lib().pospopcnt_planes16_ex(ptrs, m, n, out.data_ptr(), stream_handle(stream),
+                                            ctypes.byref(cfg) if cfg is not None else None),
+              f"pospopcnt_planes16(m={m}, n={n})")
+    return out
 
 
 def read_ceiling(x: torch.Tensor, nbytes: int | None = None, byte_offset: int = 0,
@@ -151,6 +192,7 @@ def device_info() -> dict:
             "arch": info.arch.decode()}
 
 
-__all__ = ["pospopcnt", "pospopcnt_u8", "pospopcnt_u16", "pospopcnt_u32", "pospopcnt_ptr",
+__all__ = ["pospopcnt", "pospopcnt_u8", "pospopcnt_u16", "pospopcnt_u32", "pospopcnt_u64",
+           "pospopcnt_planes", "pospopcnt_ptr",
            "read_ceiling", "histogram", "device_info", "launch_config", "stream_handle", "PpcError",
            "LaunchConfig"]

@@ -21,7 +21,7 @@ GEN_LIB = os.path.join(PKG, "inputs", "libppc_gen.so")
 
 ARCH = os.environ.get("PPC_OFFLOAD_ARCH", "gfx950")
 HIP_SOURCES = ["ppc_single.hip", "ppc_batch.hip", "ppc_api.hip", "ppc_serve.hip",
-               "ppc_onehot.hip"]
+               "ppc_onehot.hip", "ppc_wide.hip"]
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Wall", "-Wno-unused-function",

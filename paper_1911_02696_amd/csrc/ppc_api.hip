@@ -62,7 +62,7 @@ Split split_stream(const void* ptr, uint64_t nbytes, int k) {
 
 int check_stream_args(const void* ptr, uint64_t n, int k, const uint64_t* counts,
                       uint64_t* nbytes_out) {
-    if (k != 8 && k != 16 && k != 32) return PPC_ERR_WIDTH;
+    if (k != 8 && k != 16 && k != 32 && k != 64) return PPC_ERR_WIDTH;
     *nbytes_out = 0;
     if (n == 0) return PPC_OK;
     const uint64_t wb = (uint64_t)(k / 8);
@@ -89,7 +89,9 @@ const char* ppc_status_string(int status) {
     case PPC_OK: return "PPC_OK";
     case PPC_ERR_NULL: return "PPC_ERR_NULL: required pointer is NULL";
     case PPC_ERR_ALIGN: return "PPC_ERR_ALIGN: counts or descriptors not 8-byte aligned";
-    case PPC_ERR_WIDTH: return "PPC_ERR_WIDTH: word width must be 8, 16 or 32";
+    case PPC_ERR_WIDTH:
+        return "PPC_ERR_WIDTH: word width must be 8, 16, 32 or 64 (8, 16 or 32 in batches and "
+               "serving)";
     case PPC_ERR_RANGE: return "PPC_ERR_RANGE: byte length overflows 64 bits";
     case PPC_ERR_HIP: return "PPC_ERR_HIP: a HIP runtime call failed";
     case PPC_ERR_BUDGET: return "PPC_ERR_BUDGET: request exceeds the memory budget";

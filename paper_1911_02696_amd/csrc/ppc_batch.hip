@@ -642,6 +642,7 @@ int pospopcnt_each(const ppc_desc* h, uint32_t m, ppc_stream stream) {
     if (!h) return PPC_ERR_NULL;
     for (uint32_t i = 0; i < m; ++i) {
         if (h[i].reserved) return PPC_ERR_ARG;
+        if (h[i].k == 64) return PPC_ERR_WIDTH;  // as in the batched form
         uint64_t nb = 0;
         int st = check_stream_args(h[i].ptr, h[i].n, (int)h[i].k, h[i].counts, &nb);
         if (st) return st;

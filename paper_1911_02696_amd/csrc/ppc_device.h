@@ -115,6 +115,30 @@ __device__ __forceinline__ void add_plane_totals(uint32_t (&out)[C], const uint3
     }
 }
 
+// One exchange level at distance O of the reduce-scatter below, W values per lane
+// still distinct: with W > 1 the lower lane of each pair keeps (and sums) the lower
+// half of the values, the upper lane the upper half; with W = 1 it is a plain
+// butterfly.  W and O are template arguments so that every index is a constant
+// and the values stay in registers.
+template <int W, int O>
+__device__ __forceinline__ void reduce_scatter_levels(uint32_t* v, int lane) {
+    if constexpr (O >= 1) {
+        if constexpr (W > 1) {
+            const bool upper = (lane & O) != 0;
+#pragma unroll
+            for (int j = 0; j < W / 2; ++j) {
+                const uint32_t send = upper ? v[j] : v[j + W / 2];
+                const uint32_t keep = upper ? v[j + W / 2] : v[j];
+                v[j] = keep + (uint32_t)__shfl_xor((int)send, O, kWave);
+            }
+            reduce_scatter_levels<W / 2, O / 2>(v, lane);
+        } else {
+            v[0] += (uint32_t)__shfl_xor((int)v[0], O, kWave);
+            reduce_scatter_levels<1, O / 2>(v, lane);
+        }
+    }
+}
+
 // Reduce-scatter of C per-lane values over a wave: each exchange at distance
 // o = 32, 16, ... halves the values a lane keeps (the lower lane of a pair keeps
 // the lower half of the classes, the upper lane the upper half), then the last
@@ -137,24 +161,7 @@ __device__ __forceinline__ uint32_t wave_reduce_scatter(uint32_t (&v)[C], int la
         const auto r = __builtin_amdgcn_permlane16_swap(v[j], v[j + C / 4], false, false);
         v[j] = r[0] + r[1];
     }
-    int width = C / 4;
-#pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) {
-        if (width > 1) {
-            const bool upper = (lane & o) != 0;
-#pragma unroll
-            for (int j = 0; j < C / 8; ++j) {
-                if (j < width / 2) {
-                    const uint32_t send = upper ? v[j] : v[j + width / 2];
-                    const uint32_t keep = upper ? v[j + width / 2] : v[j];
-                    v[j] = keep + (uint32_t)__shfl_xor((int)send, o, kWave);
-                }
-            }
-            width >>= 1;
-        } else {
-            v[0] += (uint32_t)__shfl_xor((int)v[0], o, kWave);
-        }
-    }
+    reduce_scatter_levels<C / 4, 8>(v, lane);
     return v[0];
 }
 
@@ -290,6 +297,53 @@ __device__ __forceinline__ void csa_step(uint32_t (&B)[LOGD], uint32_t (&cnt)[C]
         d[4 * j + 3] = v[j].w;
     }
     count_classes<C>(cnt, Circuit<LOGD>::run(B, d));
+}
+
+// One stream's count, as block `block` of `blocks` working on it: the block's
+// waves take whole tiles grid-stride (Sec. 4.1 per lane, two tiles in flight),
+// the wave owning the last partial tile loads it masked, the first wave of block
+// 0 adds the head and tail dwords, and the block adds its class totals into
+// counts with rotation rot (see block_flush).  red is the block's LDS of
+// [waves][C] class totals.  Called by every thread of the block.
+template <int C, int LOGD>
+__device__ __forceinline__ void count_stream(const u32x4* __restrict__ body, uint64_t units,
+                                             const Edges& edges, int k, uint32_t rot,
+                                             unsigned long long* __restrict__ counts,
+                                             uint64_t block, uint64_t blocks,
+                                             uint32_t (*red)[C]) {
+    constexpr int U = (1 << LOGD) / 4;
+    constexpr uint64_t TILE = (uint64_t)kWave * U;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int wpb = blockDim.x / kWave;
+    const uint64_t gw = block * wpb + wave;
+    const uint64_t nw = blocks * wpb;
+    const uint64_t full = units / TILE;
+
+    uint32_t B[LOGD];
+    uint32_t cnt[C];
+#pragma unroll
+    for (int j = 0; j < LOGD; ++j) B[j] = 0;
+#pragma unroll
+    for (int i = 0; i < C; ++i) cnt[i] = 0;
+
+    walk_tiles<U>(body, full, gw, nw, lane,
+                  [&](const u32x4(&v)[U]) { csa_step<C, LOGD, U>(B, cnt, v); });
+    const uint64_t rem = units - full * TILE;
+    if (rem != 0 && gw == full % nw) {
+        u32x4 a[U];
+        load_tile_masked<U>(a, body + full * TILE + lane, lane, rem);
+        csa_step<C, LOGD, U>(B, cnt, a);
+    }
+
+    const uint32_t e = (block == 0 && wave == 0) ? edge_dword(edges, lane) : 0u;
+    uint32_t tot[C];
+    lane_totals<C, LOGD>(tot, cnt, B, e);
+    const uint32_t v = wave_reduce_scatter<C>(tot, lane);
+    constexpr int G = kWave / C;
+    if (lane % G == 0) red[wave][lane / G] = v;
+    __syncthreads();
+    block_flush<C>(red, wpb, k, rot, counts);
 }
 
 }  // namespace ppc

@@ -57,6 +57,10 @@ struct Launch {
 };
 
 // Validate and launch the single-stream kernel (the body of pospopcnt_ex).
+// k = 64 single stream (ppc_wide.hip); launch_stream routes k = 64 here.
+int launch_wide64(const void* ptr, uint64_t n, uint64_t* counts, ppc_stream stream,
+                  const ppc_launch_config* cfg);
+
 int launch_stream(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stream stream,
                   const ppc_launch_config* cfg);
 

@@ -41,40 +41,8 @@ template <int C, int LOGD>
 __global__ void __launch_bounds__(kMaxThreads)
 csa_kernel(const u32x4* __restrict__ body, uint64_t units, Edges edges, int k, uint32_t rot,
            unsigned long long* __restrict__ counts) {
-    constexpr int U = (1 << LOGD) / 4;
-    constexpr uint64_t TILE = (uint64_t)kWave * U;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    const int wpb = blockDim.x / kWave;
-    const uint64_t gw = (uint64_t)blockIdx.x * wpb + wave;
-    const uint64_t nw = (uint64_t)gridDim.x * wpb;
-    const uint64_t full = units / TILE;
-
-    uint32_t B[LOGD];
-    uint32_t cnt[C];
-#pragma unroll
-    for (int j = 0; j < LOGD; ++j) B[j] = 0;
-#pragma unroll
-    for (int i = 0; i < C; ++i) cnt[i] = 0;
-
-    walk_tiles<U>(body, full, gw, nw, lane,
-                  [&](const u32x4(&v)[U]) { csa_step<C, LOGD, U>(B, cnt, v); });
-    const uint64_t rem = units - full * TILE;
-    if (rem != 0 && gw == full % nw) {
-        u32x4 a[U];
-        load_tile_masked<U>(a, body + full * TILE + lane, lane, rem);
-        csa_step<C, LOGD, U>(B, cnt, a);
-    }
-
-    const uint32_t e = (blockIdx.x == 0 && wave == 0) ? edge_dword(edges, lane) : 0u;
-    uint32_t tot[C];
-    lane_totals<C, LOGD>(tot, cnt, B, e);
-    const uint32_t v = wave_reduce_scatter<C>(tot, lane);
     __shared__ uint32_t red[kMaxWaves][C];
-    constexpr int G = kWave / C;
-    if (lane % G == 0) red[wave][lane / G] = v;
-    __syncthreads();
-    block_flush<C>(red, wpb, k, rot, counts);
+    count_stream<C, LOGD>(body, units, edges, k, rot, counts, blockIdx.x, gridDim.x, red);
 }
 
 template <int C>
@@ -267,6 +235,7 @@ int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has
 
 int launch_stream(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stream stream,
                   const ppc_launch_config* cfg) {
+    if (k == 64) return launch_wide64(ptr, n, counts, stream, cfg);
     uint64_t nbytes = 0;
     int st = check_stream_args(ptr, n, k, counts, &nbytes);
     if (st != PPC_OK || nbytes == 0) return st;

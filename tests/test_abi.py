@@ -66,9 +66,49 @@ def test_status_strings(lib):
     assert b"unknown" in lib.ppc_status_string(12345)
 
 
-@pytest.mark.parametrize("k", [0, 1, 7, 12, 24, 64, -8])
+@pytest.mark.parametrize("k", [0, 1, 7, 12, 24, 48, 128, -8])
 def test_bad_width(lib, k):
     assert lib.pospopcnt(0x1000, 4, k, 0x8000, None) == 3  # PPC_ERR_WIDTH
+
+
+def test_k64_arguments(lib):
+    assert lib.pospopcnt_u64(None, 0, None, None) == 0
+    assert lib.pospopcnt(None, 0, 64, None, None) == 0
+    assert lib.pospopcnt_u64(None, 5, 0x8000, None) == 1
+    assert lib.pospopcnt_u64(0x1000, 5, 0x8004, None) == 2
+    assert lib.pospopcnt_u64(0x1000, 2**61, 0x8, None) == 4
+    # counts (64 x 8 bytes) ending inside the input
+    assert lib.pospopcnt_u64(0x1000, 8, 0x1000 - 64 * 8 + 8, None) == 8
+    # the ballot variant has no 64-bit form; other configuration errors as for k <= 32
+    for cfg in (L.LaunchConfig(variant=1), L.LaunchConfig(depth=12),
+                L.LaunchConfig(block_threads=512), L.LaunchConfig(grid=-1)):
+        assert lib.pospopcnt_ex(0x1000, 64, 64, 0x80000, None, ctypes.byref(cfg)) == 7
+
+
+def test_planes_arguments(lib):
+    P = ctypes.c_void_p * 40
+    planes = P(*[0x100000 * (j + 1) for j in range(40)])
+    assert lib.pospopcnt_planes16(planes, 0, 10, 0x8000, None) == 7
+    assert lib.pospopcnt_planes16(planes, L.MAX_PLANES + 1, 10, 0x8000, None) == 7
+    assert lib.pospopcnt_planes16(planes, 4, 0, None, None) == 0  # nothing to count
+    assert lib.pospopcnt_planes16(None, 4, 10, 0x8000, None) == 1
+    assert lib.pospopcnt_planes16(planes, 4, 10, None, None) == 1
+    with_null = P(*([0x100000, 0] + [0x300000] * 38))
+    assert lib.pospopcnt_planes16(with_null, 2, 10, 0x8000, None) == 1
+    assert lib.pospopcnt_planes16(planes, 4, 10, 0x8003, None) == 2
+    assert lib.pospopcnt_planes16(planes, 4, 2**63, 0x8, None) == 4
+    # counts (4 x 16 x 8 bytes) overlapping the third plane
+    assert lib.pospopcnt_planes16(planes, 4, 10, 0x300000 + 8, None) == 8
+    cfg = L.LaunchConfig(variant=1)
+    assert lib.pospopcnt_planes16_ex(planes, 4, 10, 0x8000, None, ctypes.byref(cfg)) == 7
+
+
+def test_batched_forms_reject_k64(lib):
+    import numpy as np
+    descs = np.zeros(1, dtype=[("ptr", "<u8"), ("n", "<u8"), ("k", "<u4"), ("reserved", "<u4"),
+                               ("counts", "<u8")])
+    descs[0] = (0x1000, 4, 64, 0, 0x80000)
+    assert lib.pospopcnt_each(descs.ctypes.data, 1, None) == 3
 
 
 def test_zero_length_is_a_no_op(lib):
