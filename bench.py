@@ -327,6 +327,67 @@ def onehot_leg(args, torch, api):
     return out, ok
 
 
+def wide_leg(args, torch, api):
+    """Words wider than 32 bits (Sec. 4), 16 GiB per launch: one stream of 2^31 64-bit
+    words, and 64-bit words held as 4 planes of 2^31 16-bit limbs (4 GiB each).  Bits
+    are Bernoulli(0.5).  Checked against the oracle on the first 256 MiB of each
+    stream or plane, and by the total count over the passes."""
+    import oracle
+    out, ok = {}, True
+    nbytes = 1 << 34
+    stream = torch.cuda.current_stream()
+    dist = I.Dist.uniform()
+    sample = 1 << 28
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / args.steps
+
+    passes = args.warmup + args.steps
+    dev = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    upload(dev, nbytes, dist, SEED + 7)
+    n = nbytes // 8
+    counts = torch.zeros(64, dtype=torch.int64, device="cuda")
+    t = timed(lambda: api.pospopcnt_u64(dev, n=n, out=counts))
+    one = api.pospopcnt_u64(dev, n=n).cpu().numpy()
+    host = I.generate(sample, dist, SEED + 7)
+    exp = oracle.count(host, sample // 8, 64, threads=I.default_threads()).astype(np.int64)
+    g = api.pospopcnt_u64(dev, n=sample // 8).cpu().numpy()
+    good = bool((g == exp).all()) and bool((counts.cpu().numpy() == one * passes).all())
+    ok &= good
+    out["u64_2p31"] = {"bytes": nbytes, "words": n, "gbps": round(nbytes / t / 1e9, 1),
+                       "frac_of_hbm_peak": round(nbytes / t / 1e9 / HBM_PEAK_GBPS, 4),
+                       "ms": round(t * 1e3, 4), "check": good}
+    m = 4
+    per = nbytes // m
+    planes = [dev[j * per:(j + 1) * per] for j in range(m)]
+    for j in range(m):
+        upload(planes[j], per, dist, SEED + 8 + j)
+    n = per // 2
+    counts = torch.zeros(16 * m, dtype=torch.int64, device="cuda")
+    t = timed(lambda: api.pospopcnt_planes(planes, n=n, out=counts))
+    one = api.pospopcnt_planes(planes, n=n).cpu().numpy()
+    hosts = [I.generate(sample, dist, SEED + 8 + j) for j in range(m)]
+    exp = oracle.get().count_planes(hosts, sample // 2).astype(np.int64)
+    g = api.pospopcnt_planes(planes, n=sample // 2).cpu().numpy()
+    good = bool((g == exp).all()) and bool((counts.cpu().numpy() == one * passes).all())
+    ok &= good
+    out["planes16_4x2p31"] = {"bytes": nbytes, "words": n, "k": 16 * m,
+                              "gbps": round(nbytes / t / 1e9, 1),
+                              "frac_of_hbm_peak": round(nbytes / t / 1e9 / HBM_PEAK_GBPS, 4),
+                              "ms": round(t * 1e3, 4), "check": good}
+    del dev, planes
+    torch.cuda.empty_cache()
+    return out, ok
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,9 +403,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 20,000-stream batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
-    ap.add_argument("--legs", default="single,batched,serving,onehot",
-                    help="comma-separated subset of single,batched,serving,onehot to run (the "
-                         "full JSON line is printed only when the single leg runs)")
+    ap.add_argument("--legs", default="single,batched,serving,onehot,wide",
+                    help="comma-separated subset of single,batched,serving,onehot,wide to run "
+                         "(the full JSON line is printed only when the single leg runs)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-reference", type=int, default=0, metavar="BYTES",
@@ -373,8 +434,8 @@ def main():
         return
 
     legs = set(args.legs.split(","))
-    if not legs <= {"single", "batched", "serving", "onehot"}:
-        ap.error("--legs takes single, batched, serving and onehot")
+    if not legs <= {"single", "batched", "serving", "onehot", "wide"}:
+        ap.error("--legs takes single, batched, serving, onehot and wide")
     args.no_batched |= "batched" not in legs
     args.no_serving |= "serving" not in legs
     if "single" not in legs:
@@ -382,6 +443,8 @@ def main():
         out = {}
         if "onehot" in legs:
             out["onehot"] = onehot_leg(args, torch, api)[0]
+        if "wide" in legs:
+            out["wide"] = wide_leg(args, torch, api)[0]
         if not args.no_batched:
             out["batched"] = batched_leg(args, torch, api)[0]
         if not args.no_serving:
@@ -492,6 +555,9 @@ def main():
     onehot, ok_onehot = None, True
     if "onehot" in legs:
         onehot, ok_onehot = onehot_leg(args, torch, api)
+    wide, ok_wide = None, True
+    if "wide" in legs:
+        wide, ok_wide = wide_leg(args, torch, api)
 
     achieved = nbytes / avg_kernel / 1e9
     src_hash = kernel_source_hash()
@@ -529,6 +595,7 @@ def main():
         "batched": batched,
         "serving": serving,
         "histogram": onehot,
+        "wide": wide,
         "cpu_baseline": cpu,
         "check": {"total_equals_passes_times_one_pass": ok_total,
                   "sample_equals_oracle": ok_sample},
@@ -536,7 +603,8 @@ def main():
                    "clock_mhz": info["clock_khz"] / 1000},
     }
     print(json.dumps(line), flush=True)
-    if not ok_total or ok_sample is False or not ok_batched or not ok_serving or not ok_onehot:
+    if not ok_total or ok_sample is False or not ok_batched or not ok_serving or not ok_onehot \
+            or not ok_wide:
         sys.exit(1)
 
 
