@@ -12,7 +12,10 @@
 // Two kernels per call:
 //   batch_prep  (one block): validates the descriptors, scans their weights into
 //               cum[0..m] and, for every block, records the first position its
-//               share touches, into first[0..G);
+//               share touches, into first[0..G);  above 4096 streams the same
+//               work is split over one block per 2048 positions (prep_chunks,
+//               then prep_finish), since a single compute unit is slow to load
+//               and weigh tens of thousands of descriptors;
 //   batch_main  (G blocks): each block walks the streams of its share; for each
 //               it runs the CSA core of the single-stream kernel over its piece of
 //               the body (the block's waves take its 64-lane tiles in turn), the
@@ -50,6 +53,8 @@ struct ppc_plan {
     uint64_t* cum = nullptr;                  // [max_streams + 1]
     uint32_t* first = nullptr;                // [gmax]
     uint32_t* rejected = nullptr;             // [1]
+    uint64_t* part = nullptr;                 // [chunks]: weight of each prep chunk
+    uint32_t* part_bad = nullptr;             // [chunks]: rejected descriptors per chunk
     unsigned long long* sink = nullptr;       // [gmax][32], autotune target, one row per block
     ppc_batch_config cfg{};
     int cfg_version = 0;
@@ -254,6 +259,118 @@ batch_prep(const ppc_desc* __restrict__ descs, uint32_t m, uint64_t weight, uint
     }
 }
 
+// ---- batch preparation over several blocks (more than kPrepLdsPositions streams)
+
+constexpr uint32_t kChunk = 2 * kPrepThreads;  // positions per block
+
+// Smallest block b in [0, G] whose share starts at or after axis position c
+// (c <= total); block b's share starts at b * base + min(b, extra).
+__device__ __forceinline__ uint32_t share_at_or_after(uint64_t c, uint64_t total, uint64_t G) {
+    const uint64_t base = total / G, extra = total % G;
+    if (base == 0) return (uint32_t)c;
+    const uint64_t wide = extra * (base + 1);  // blocks 0 .. extra-1 take base + 1
+    if (c <= wide) return (uint32_t)((c + base) / (base + 1));
+    return (uint32_t)(extra + (c - wide + base - 1) / base);
+}
+
+// Pass 1: the weight of every position of this block's chunk into cum, the chunk's
+// total into part[chunk], its rejected descriptors into part_bad[chunk].  Both
+// descriptor loads of a thread are in flight together.
+__global__ void __launch_bounds__(kPrepThreads)
+prep_chunks(const ppc_desc* __restrict__ descs, uint32_t m, uint64_t weight, uint64_t* cum,
+            uint64_t* part, uint32_t* part_bad, int zero_counts) {
+    __shared__ uint64_t sh[kPrepThreads / kWave];
+    __shared__ uint32_t bad_total;
+    if (threadIdx.x == 0) bad_total = 0;
+    const uint32_t base = blockIdx.x * kChunk;
+    ppc_desc d[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const uint32_t i = base + r * kPrepThreads + threadIdx.x;
+        if (i < m) d[r] = descs[stream_at(i, m)];
+    }
+    uint64_t local = 0;
+    uint32_t bad = 0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const uint32_t i = base + r * kPrepThreads + threadIdx.x;
+        if (i < m) {
+            const uint64_t w = weight_of(d[r], weight, &bad);
+            cum[i] = w;
+            local += w;
+            if (zero_counts && w)
+                for (uint32_t p = 0; p < d[r].k; ++p) d[r].counts[p] = 0;
+        }
+    }
+    uint64_t total;
+    (void)block_exclusive_scan(local, &total, sh);  // its barriers order bad_total too
+    if (bad) atomicAdd(&bad_total, bad);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = total;
+        part_bad[blockIdx.x] = bad_total;
+    }
+}
+
+// Pass 2, one block per chunk: the chunk's offset on the axis (the weights of the
+// chunks before it), the exclusive prefix sums of its positions into cum (and into
+// LDS), and first[b] for every block b whose share starts inside the chunk's range
+// of the axis, by binary search in LDS.  The last chunk writes cum[m], the rejected
+// count, and first[b] = m - 1 for the shares that start at the end of the axis
+// (when the axis is shorter than the grid).
+__global__ void __launch_bounds__(kPrepThreads)
+prep_finish(uint32_t m, uint64_t* cum, const uint64_t* __restrict__ part,
+            const uint32_t* __restrict__ part_bad, uint32_t chunks, uint32_t* first, uint32_t G,
+            uint32_t* rejected) {
+    __shared__ uint64_t sh[kPrepThreads / kWave];
+    __shared__ uint64_t lcum[kChunk];
+    const uint32_t c = blockIdx.x, T = blockDim.x;
+    uint64_t before = 0, all = 0;
+    uint32_t bad = 0;
+    for (uint32_t j = threadIdx.x; j < chunks; j += T) {
+        all += part[j];
+        if (j < c) before += part[j];
+        bad += part_bad[j];
+    }
+    uint64_t off, total;
+    (void)block_exclusive_scan(before, &off, sh);
+    (void)block_exclusive_scan(all, &total, sh);
+    const uint32_t base = c * kChunk;
+    const uint32_t n = min(kChunk, m - base);
+    const uint32_t p = 2 * threadIdx.x;
+    const uint64_t w0 = p < n ? cum[base + p] : 0, w1 = p + 1 < n ? cum[base + p + 1] : 0;
+    uint64_t chunk_total;
+    const uint64_t c0 = off + block_exclusive_scan(w0 + w1, &chunk_total, sh);
+    if (p < n) {
+        cum[base + p] = c0;
+        lcum[p] = c0;
+    }
+    if (p + 1 < n) {
+        cum[base + p + 1] = c0 + w0;
+        lcum[p + 1] = c0 + w0;
+    }
+    if (c == chunks - 1) {
+        if (threadIdx.x == 0) cum[m] = total;
+        uint64_t nb;
+        (void)block_exclusive_scan(bad, &nb, sh);
+        if (threadIdx.x == 0) rejected[0] = (uint32_t)nb;
+        for (uint32_t b = share_at_or_after(total, total, G) + threadIdx.x; b < G; b += T)
+            first[b] = m - 1;
+    }
+    __syncthreads();
+    if (chunk_total == 0) return;
+    const uint32_t b1 = min(share_at_or_after(off + chunk_total, total, G), G);
+    for (uint32_t b = share_at_or_after(off, total, G) + threadIdx.x; b < b1; b += T) {
+        const uint64_t lo = share_lo(b, total, G);
+        uint32_t l = 0, h = n;  // last position l < n of the chunk with lcum[l] <= lo
+        while (h - l > 1) {
+            const uint32_t mid = l + (h - l) / 2;
+            if (lcum[mid] <= lo) l = mid; else h = mid;
+        }
+        first[b] = base + l;
+    }
+}
+
 // descs, cum and first are read-only for the whole launch and never alias the
 // counters, which lets the per-stream bookkeeping use scalar loads.  sink, when
 // not NULL, receives every flush instead of the descriptors' counters, in one
@@ -378,9 +495,21 @@ static int enqueue(ppc_plan* pl, const ppc_desc* descs, uint32_t m, hipStream_t 
     const ppc_batch_config& c = pl->cfg;
     uint32_t G = (uint32_t)(c.blocks_per_cu * pl->cus);
     uint64_t weight = (uint64_t)c.stream_weight;
-    void* pargs[] = {(void*)&descs, &m,       &weight,       &pl->cum,
-                     &pl->first,    &G,       &pl->rejected, &zero_counts};
-    PPC_HIP(hipLaunchKernel((const void*)batch_prep, dim3(1), dim3(kPrepThreads), pargs, 0, s));
+    if (m <= kPrepLdsPositions) {
+        void* pargs[] = {(void*)&descs, &m,       &weight,       &pl->cum,
+                         &pl->first,    &G,       &pl->rejected, &zero_counts};
+        PPC_HIP(hipLaunchKernel((const void*)batch_prep, dim3(1), dim3(kPrepThreads), pargs, 0, s));
+    } else {
+        uint32_t chunks = (m + kChunk - 1) / kChunk;
+        void* a1[] = {(void*)&descs, &m, &weight, &pl->cum, &pl->part, &pl->part_bad, &zero_counts};
+        PPC_HIP(hipLaunchKernel((const void*)prep_chunks, dim3(chunks), dim3(kPrepThreads), a1, 0, s));
+        const uint64_t* part = pl->part;
+        const uint32_t* part_bad = pl->part_bad;
+        void* a2[] = {&m, &pl->cum, (void*)&part, (void*)&part_bad, &chunks, &pl->first, &G,
+                      &pl->rejected};
+        PPC_HIP(hipLaunchKernel((const void*)prep_finish, dim3(chunks), dim3(kPrepThreads), a2, 0,
+                                s));
+    }
     const uint64_t* cum = pl->cum;
     const uint32_t* first = pl->first;
     void* margs[] = {(void*)&descs, (void*)&cum, (void*)&first, &weight, &sink, &m};
@@ -440,7 +569,10 @@ int ppc_plan_create(const ppc_workload_hint* hint, ppc_plan** out) {
     const size_t off_first = (cum_bytes + 255) & ~(size_t)255;
     const size_t off_rej = (off_first + first_bytes + 255) & ~(size_t)255;
     const size_t off_sink = off_rej + 256;
-    const size_t total = off_sink + (size_t)pl->gmax * 32 * 8;
+    const size_t chunks = ((size_t)hint->max_streams + kChunk - 1) / kChunk;
+    const size_t off_part = off_sink + (size_t)pl->gmax * 32 * 8;
+    const size_t off_part_bad = off_part + ((chunks * 8 + 255) & ~(size_t)255);
+    const size_t total = off_part_bad + chunks * 4;
     hipError_t e = hipMalloc(&pl->scratch, total);
     if (e != hipSuccess) {
         delete pl;
@@ -451,6 +583,8 @@ int ppc_plan_create(const ppc_workload_hint* hint, ppc_plan** out) {
     pl->first = (uint32_t*)(base + off_first);
     pl->rejected = (uint32_t*)(base + off_rej);
     pl->sink = (unsigned long long*)(base + off_sink);
+    pl->part = (uint64_t*)(base + off_part);
+    pl->part_bad = (uint32_t*)(base + off_part_bad);
     e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         (void)hipFree(pl->scratch);

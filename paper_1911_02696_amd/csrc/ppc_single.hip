@@ -138,19 +138,22 @@ static StreamKernel csa_table[3][3] = {
 static StreamKernel ballot_table[3] = {ballot_kernel<8>, ballot_kernel<16>, ballot_kernel<32>};
 static CeilKernel ceil_table[3] = {ceiling_kernel<3>, ceiling_kernel<4>, ceiling_kernel<5>};
 
-// Default launch shape per width, measured on MI355X over 2-16 GiB inputs: a
-// circuit of 16 dwords per lane per step (as many inputs as the paper's 1 kB
-// circuit) and few waves -- 3 to 4 per compute unit, each with two 4 KiB tiles in
-// flight, about 8 MiB in flight over the chip.  More resident waves lower the
-// achieved bandwidth (6.9 TB/s at full occupancy against 7.2 TB/s).
+// Default launch shape per width and size, measured on MI355X over 256 MiB - 16 GiB
+// inputs: a circuit of 16 dwords per lane per step (as many inputs as the paper's
+// 1 kB circuit) and few waves -- 3 to 4 per compute unit, each with two 4 KiB tiles
+// in flight, about 8 MiB in flight over the chip.  More resident waves lower the
+// achieved bandwidth (6.9 TB/s at full occupancy against 7.2 TB/s).  Above 1 GiB,
+// 8- and 32-bit words do best with three 64-thread blocks per CU; up to 1 GiB, and
+// for 16-bit words at every size, one 256-thread block per CU (for 256 MiB of u32
+// words 6.3 TB/s against 4.9).
 struct Shape {
     int logd, threads, waves_per_cu;
 };
-static Shape default_shape(int k) {
-    if (k == 16) return {4, 256, 4};
+static Shape default_shape(int k, uint64_t nbytes) {
+    if (k == 16 || nbytes <= (1ull << 30)) return {4, 256, 4};
     return {4, 64, 3};
 }
-static int default_logd(int k) { return default_shape(k).logd; }
+static int default_logd(int k) { return default_shape(k, 0).logd; }
 
 // Resident blocks per CU of a kernel at a block size (cached).
 static int occupancy(const void* kernel, int threads) {
@@ -190,7 +193,7 @@ int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has
         else if (c.depth == 32) logd = 5;
         else return PPC_ERR_ARG;
     }
-    const Shape shape = default_shape(k);
+    const Shape shape = default_shape(k, nbytes);
     const int threads = c.block_threads ? c.block_threads : shape.threads;
     if (threads < kWave || threads > kMaxThreads || threads % kWave) return PPC_ERR_ARG;
     if (c.blocks_per_cu < 0 || c.grid < 0) return PPC_ERR_ARG;

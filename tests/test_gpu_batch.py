@@ -228,3 +228,54 @@ def test_tiny_totals_smaller_than_the_grid(weight):
         plan.run(bt.descs)
         torch.cuda.synchronize()
         bt.check()
+
+
+@pytest.mark.parametrize("m", [4096, 4097, 6143, 6144, 6145, 10_241])
+def test_many_streams_split_preparation(m):
+    """Batches above 4096 streams are prepared by one block per 2048 positions: sizes
+    at and around those boundaries, with empty and rejected descriptors among them
+    (the rejected count sums over the chunks), with and without graph replay."""
+    s = mixed(m, 9, SEED + 40 + m)
+    s.lengths[::97] = 0
+    bt = Batch(s, SEED + 40 + m)
+    d = bt.desc_host.copy()
+    bad = list(range(3, m, 1001))
+    d[bad, 2] = 24  # width not 8/16/32
+    for graph in (False, True):
+        say(f"split preparation m={m} graph={graph}")
+        bt.counts.zero_()
+        plan = B.Plan(m, graph=graph)
+        plan.run(B.to_device(d))
+        torch.cuda.synchronize()
+        assert plan.rejected() == len(bad)
+        got = bt.counts.cpu().numpy()
+        for i in range(m):
+            k = int(s.ks[i])
+            exp = 0 if i in bad else bt.expected(i)
+            assert (got[i, :k] == exp).all(), f"stream {i}"
+
+
+def test_many_streams_short_axis_and_one_long_stream():
+    """5000 descriptors: mostly empty with a few one-word streams (an axis shorter
+    than the grid), then one long stream among the empty ones."""
+    m = 5000
+    lengths = np.zeros(m, np.uint64)
+    lengths[[17, 2500, 4999]] = 1
+    s = I.StreamSet(lengths, np.full(m, 16, np.int32), np.full(m, 0.5))
+    bt = Batch(s, SEED + 50)
+    for cfg in (dict(blocks_per_cu=16, block_threads=64), dict(stream_weight=1)):
+        bt.counts.zero_()
+        plan = B.Plan(m)
+        plan.config = cfg
+        say(f"short axis m={m} cfg={cfg}")
+        plan.run(bt.descs)
+        torch.cuda.synchronize()
+        bt.check(which=[17, 2500, 4999, 0, 1, 4998])
+    lengths[2500] = (1 << 24) + 5
+    s = I.StreamSet(lengths, np.full(m, 16, np.int32), np.full(m, 0.5))
+    bt = Batch(s, SEED + 51)
+    plan = B.Plan(m)
+    say(f"one long stream among {m}")
+    plan.run(bt.descs)
+    torch.cuda.synchronize()
+    bt.check(which=[17, 2500, 4999, 0, 4998])
