@@ -491,9 +491,10 @@ static int check_config(const ppc_batch_config& c) {
 }
 
 static int enqueue(ppc_plan* pl, const ppc_desc* descs, uint32_t m, hipStream_t s,
-                   unsigned long long* sink, int zero_counts = 0) {
+                   unsigned long long* sink, int zero_counts = 0, uint32_t max_blocks = 0) {
     const ppc_batch_config& c = pl->cfg;
     uint32_t G = (uint32_t)(c.blocks_per_cu * pl->cus);
+    if (max_blocks && max_blocks < G) G = max_blocks;
     uint64_t weight = (uint64_t)c.stream_weight;
     if (m <= kPrepLdsPositions) {
         void* pargs[] = {(void*)&descs, &m,       &weight,       &pl->cum,
@@ -538,12 +539,24 @@ using namespace ppc;
 namespace ppc {
 // The batched count with every valid descriptor's counters cleared first, for
 // callers whose descriptors own distinct counters (the serving executor); never
-// captured into a graph.
-int batch_fresh(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s) {
+// captured into a graph.  With the batch's input bytes known (bytes > 0), the grid
+// is cut to about one block per kFreshUnitsPerBlock weighted units: a small batch
+// spread over the whole grid would split each stream over hundreds of blocks,
+// whose flushes then queue on the same few counters.
+constexpr uint64_t kFreshUnitsPerBlock = 1024;  // 16 KiB of body per one-wave block
+
+int batch_fresh(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s,
+                uint64_t bytes) {
     if (!pl || !d_descs) return PPC_ERR_NULL;
     if (m == 0) return PPC_OK;
     if (m > pl->max_streams) return PPC_ERR_ARG;
-    return enqueue(pl, d_descs, m, s, nullptr, 1);
+    uint32_t max_blocks = 0;
+    if (bytes) {
+        const uint64_t units = (uint64_t)m * (uint64_t)pl->cfg.stream_weight + bytes / 16;
+        const uint64_t want = (units + kFreshUnitsPerBlock - 1) / kFreshUnitsPerBlock;
+        max_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 1u << 30);
+    }
+    return enqueue(pl, d_descs, m, s, nullptr, 1, max_blocks);
 }
 }  // namespace ppc
 

@@ -65,8 +65,10 @@ int launch_stream(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stre
                   const ppc_launch_config* cfg);
 
 // pospopcnt_batch without graph capture, clearing each valid descriptor's
-// counters before counting (the descriptors must own distinct counters).
-int batch_fresh(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, hipStream_t stream);
+// counters before counting (the descriptors must own distinct counters).  bytes:
+// the batch's input bytes if known (sizes the grid for small batches), else 0.
+int batch_fresh(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, hipStream_t stream,
+                uint64_t bytes);
 
 int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has_edges,
                    uint64_t nbytes, Launch* out);

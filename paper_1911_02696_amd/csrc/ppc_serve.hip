@@ -275,8 +275,12 @@ class HipExecutor : public Executor {
         Slot& s = slots_[si];
         const uint32_t n = (uint32_t)items.size();
         hipStream_t st = streams_[s.stream];
-        CopySeg* h_segs = (CopySeg*)(s.h_meta + seg_base_);
-        uint64_t units = 0;
+        // the copy segments follow this batch's descriptors, so that the one
+        // host-to-device copy stays small (large ones go through a DMA engine, whose
+        // hand-over to the compute queue costs tens of microseconds)
+        const size_t seg_off = (sizeof(ppc_desc) * n + 255) & ~(size_t)255;
+        CopySeg* h_segs = (CopySeg*)(s.h_meta + seg_off);
+        uint64_t units = 0, bytes = 0;
         for (uint32_t i = 0; i < n; ++i) {
             const Admitted& a = items[i];
             uint8_t* dst = in_place_ ? nullptr : (uint8_t*)arena_ + a.off;
@@ -286,12 +290,13 @@ class HipExecutor : public Executor {
             }
             s.h_descs()[i] = {in_place_ ? a.r.src : (const void*)dst, a.r.n, a.r.k, 0,
                               s.d_counts + 32ull * i};
+            bytes += a.bytes;
         }
         // one copy of the descriptors (and the copy segments right after them)
-        const size_t meta = in_place_ ? sizeof(ppc_desc) * n : seg_base_ + sizeof(CopySeg) * n;
+        const size_t meta = in_place_ ? sizeof(ppc_desc) * n : seg_off + sizeof(CopySeg) * n;
         PPC_HIP(hipMemcpyAsync(s.d_meta, s.h_meta, meta, hipMemcpyHostToDevice, st));
         if (units) {
-            const CopySeg* d_segs = (const CopySeg*)(s.d_meta + seg_base_);
+            const CopySeg* d_segs = (const CopySeg*)(s.d_meta + seg_off);
             // about 16 KiB per block, at most 8 blocks per compute unit
             const uint64_t want = (units + 1023) / 1024;
             const uint32_t grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)cus_ * 8);
@@ -299,7 +304,7 @@ class HipExecutor : public Executor {
             PPC_HIP(hipLaunchKernel((const void*)copy_segments, dim3(grid), dim3(256), args, 0, st));
         }
         // counts are cleared by the batch's own prefix kernel
-        const int bst = batch_fresh(plans_[s.stream], s.d_descs(), n, st);
+        const int bst = batch_fresh(plans_[s.stream], s.d_descs(), n, st, bytes);
         if (bst) return bst;
         PPC_HIP(hipMemcpyAsync(s.h_counts, s.d_counts, 256ull * n, hipMemcpyDeviceToHost, st));
         PPC_HIP(hipEventRecord(s.done, st));
