@@ -12,6 +12,13 @@ read-only ceiling kernel on the same buffer, and the CPU oracle timed on a
 bounded sample of the same input.  After timing, the counts are checked:
 the total equals (warmup + steps) times one pass, and the GPU counts of the
 sample equal the oracle's.
+
+Further legs, reported in the same line (each checked against the oracle on a
+sample): 20,000 uneven streams in one batched launch against one launch per
+stream ("batched"), a Poisson request trace through the serving loop with
+latency percentiles ("serving"), the histogram of categorical ids through their
+one-hot codes ("histogram"), and 64-bit words, plain and as 16-bit planes
+("wide").  --legs selects a subset.
 """
 from __future__ import annotations
 
@@ -415,8 +422,8 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
-              "(the count shards by byte range with one 256-byte sum per GPU, which this "
-              "build does not run).", file=sys.stderr)
+              "(the count would shard by byte range with one 256-byte sum per GPU; only the "
+              "one-GPU path is implemented).", file=sys.stderr)
         sys.exit(2)
 
     import torch
