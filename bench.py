@@ -521,6 +521,23 @@ def main():
         ceiling = {"kernel": "ceiling_kernel (XOR of the same loads)",
                    "gbps": round(nbytes / c_avg / 1e9, 1),
                    "frac_of_peak": round(nbytes / c_avg / 1e9 / HBM_PEAK_GBPS, 4)}
+        # Context from a library kernel: torch's int64 sum over the same bytes, a plain
+        # streaming reduction that none of this code touches.
+        words = nbytes // 8
+        lib_views = [v[:8 * words].view(torch.int64) for v in views]
+        for i in range(args.warmup):
+            lib_views[i % copies].sum()
+        lev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        lev[0].record(stream)
+        for i in range(args.steps):
+            lib_views[(args.warmup + i) % copies].sum()
+        lev[1].record(stream)
+        torch.cuda.synchronize()
+        l_avg = lev[0].elapsed_time(lev[1]) / 1e3 / args.steps
+        ceiling["library_read_reference"] = {
+            "kernel": "torch int64 sum of the same bytes",
+            "gbps": round(8 * words / l_avg / 1e9, 1),
+            "frac_of_peak": round(8 * words / l_avg / 1e9 / HBM_PEAK_GBPS, 4)}
 
     cpu = None
     ok_sample = None
