@@ -8,7 +8,8 @@
 // turns them into packed one-hot codes in registers (see Codes: four 8-bit, two
 // 16-bit or one 32-bit code per dword; ids >= bins have no code and are tallied
 // apart), and feeds the code dwords of a tile to one Harley-Seal circuit of
-// Sec. 2, whose carry is counted per category class as in the counting kernel.
+// Sec. 2, whose carry enters the cross-tile levels of ppc_tree.h before it is
+// counted per category class as in the counting kernel.
 // Head and tail ids outside the 16-byte aligned body are expanded one per lane by
 // the first wave; padding never becomes an id.
 #include "ppc_device.h"
@@ -116,8 +117,8 @@ struct Codes {
 
 template <int C, int IDB, int LOGD>
 __device__ __forceinline__ uint32_t onehot_step(uint32_t (&B)[LOGD], uint32_t& other,
-                                                const u32x4 (&v)[4],
-                                            const bool (&valid)[4], bool maybe_partial) {
+                                                const u32x4 (&v)[4], const bool (&valid)[4],
+                                                bool maybe_partial) {
     using K = Codes<C, IDB>;
     static_assert(K::NCODE == (1 << LOGD), "one circuit per tile");
     uint32_t in[K::NIN];
