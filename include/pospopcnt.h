@@ -206,9 +206,10 @@ enum { PPC_PLAN_GRAPH = 1 };
 typedef struct ppc_plan ppc_plan;
 
 /* Creates a plan on the current device.  The plan owns device scratch for
- * max_streams descriptors (a prefix array, 8 bytes per stream, a per-block
- * start table and a 1 MiB autotuning sink) and a default configuration.  This is the only batched
- * call that allocates.  Errors: PPC_ERR_NULL, PPC_ERR_ARG (max_streams = 0 or
+ * max_streams descriptors (a prefix array of 8 bytes per stream, 12 bytes per
+ * 2048 streams for the split preparation, a per-block start table and a 1 MiB
+ * autotuning sink) and a default configuration.  This is the only batched call
+ * that allocates.  Errors: PPC_ERR_NULL, PPC_ERR_ARG (max_streams = 0 or
  * > 2^26), PPC_ERR_HIP. */
 int ppc_plan_create(const ppc_workload_hint* hint, ppc_plan** plan);
 
@@ -216,9 +217,10 @@ int ppc_plan_create(const ppc_workload_hint* hint, ppc_plan** plan);
  * completed.  NULL is accepted. */
 int ppc_plan_destroy(ppc_plan* plan);
 
-/* Counts every stream of the m descriptors at d_descs (device memory) in one
- * prefix kernel and one persistent counting kernel, asynchronously on stream.
- * With PPC_PLAN_GRAPH the two kernels are captured into a HIP graph on the first
+/* Counts every stream of the m descriptors at d_descs (device memory) with a
+ * preparation kernel (two above 4096 streams: one block per 2048 streams) and
+ * one persistent counting kernel, asynchronously on stream.  With
+ * PPC_PLAN_GRAPH the kernels are captured into a HIP graph on the first
  * call for a given (d_descs, m, configuration) and replayed by later calls; the
  * graph reads the descriptors when it runs, so their contents may change between
  * calls.  Calls sharing a plan must not overlap in time (the plan's scratch is
@@ -252,7 +254,8 @@ int ppc_plan_rejected(ppc_plan* plan, ppc_stream stream, uint32_t* rejected);
  * (each launch as pospopcnt with default configuration).  The per-launch form
  * the batched kernel is measured against; also handy when descriptors are
  * built on the host.  Validation is per descriptor, before any launch: the
- * first invalid descriptor's status is returned and nothing is launched. */
+ * first invalid descriptor's status is returned and nothing is launched; as in
+ * the batched form, k must be 8, 16 or 32 (PPC_ERR_WIDTH for 64). */
 int pospopcnt_each(const ppc_desc* h_descs, uint32_t m, ppc_stream stream);
 
 /* ------------------------------------------------------------------------
