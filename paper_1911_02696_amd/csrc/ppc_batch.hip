@@ -540,10 +540,10 @@ namespace ppc {
 // The batched count with every valid descriptor's counters cleared first, for
 // callers whose descriptors own distinct counters (the serving executor); never
 // captured into a graph.  With the batch's input bytes known (bytes > 0), the grid
-// is cut to about one block per kFreshUnitsPerBlock weighted units: a small batch
+// is cut to about kFreshUnitsPerWave weighted units per wave: a small batch
 // spread over the whole grid would split each stream over hundreds of blocks,
 // whose flushes then queue on the same few counters.
-constexpr uint64_t kFreshUnitsPerBlock = 1024;  // 16 KiB of body per one-wave block
+constexpr uint64_t kFreshUnitsPerWave = 1024;  // 16 KiB of body per wave
 
 int batch_fresh(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s,
                 uint64_t bytes) {
@@ -553,7 +553,8 @@ int batch_fresh(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s
     uint32_t max_blocks = 0;
     if (bytes) {
         const uint64_t units = (uint64_t)m * (uint64_t)pl->cfg.stream_weight + bytes / 16;
-        const uint64_t want = (units + kFreshUnitsPerBlock - 1) / kFreshUnitsPerBlock;
+        const uint64_t per_block = kFreshUnitsPerWave * (uint64_t)(pl->cfg.block_threads / kWave);
+        const uint64_t want = (units + per_block - 1) / per_block;
         max_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 1u << 30);
     }
     return enqueue(pl, d_descs, m, s, nullptr, 1, max_blocks);

@@ -223,6 +223,12 @@ class HipExecutor : public Executor {
             ppc_workload_hint hint{c.max_batch, 0};
             st = ppc_plan_create(&hint, &plans_[i]);
             if (st) return st;
+            // Four-wave blocks, one per compute unit: a request split over the grid
+            // then flushes from a quarter as many blocks (the waves of a block sum
+            // in LDS first), and the flush atomics on its counters queue less.
+            const ppc_batch_config serve_cfg{16, 256, 1, 4096};
+            st = ppc_plan_set_config(plans_[i], &serve_cfg);
+            if (st) return st;
         }
         slots_.resize((size_t)c.streams * 2);
         seg_base_ = (sizeof(ppc_desc) * c.max_batch + 255) & ~(size_t)255;
