@@ -69,6 +69,7 @@ struct ppc_plan {
 namespace ppc {
 
 constexpr int kBatchMaxThreads = 256;
+constexpr int kBatchClasses = 32;  // dword-bit classes of the batched kernel
 constexpr int kPrepThreads = 1024;
 constexpr uint32_t kMaxPlanStreams = 1u << 26;
 constexpr int kMaxBlocksPerCu = 16;
@@ -376,12 +377,16 @@ prep_finish(uint32_t m, uint64_t* cum, const uint64_t* __restrict__ part,
 // not NULL, receives every flush instead of the descriptors' counters, in one
 // row of 32 per block (so that timing runs see the same atomic traffic as real
 // ones, spread over many addresses).
-template <int LOGD>
-__global__ void __launch_bounds__(kBatchMaxThreads)
-batch_main(const ppc_desc* __restrict__ descs, const uint64_t* __restrict__ cum,
-           const uint32_t* __restrict__ first, uint64_t weight, unsigned long long* sink,
-           uint32_t m) {
-    constexpr int C = 32;
+// The block's share [lo, hi) of the axis: every stream it touches, from position
+// pos on, counted into the stream's counters (or into sink).  cum: the prefix
+// array, in global memory or in LDS.
+template <int LOGD, typename Cum>
+__device__ __forceinline__ void walk_share(const ppc_desc* __restrict__ descs, Cum cum,
+                                           uint32_t pos, uint32_t m, uint64_t lo, uint64_t hi,
+                                           uint64_t weight, unsigned long long* sink,
+                                           uint64_t b,
+                                           unsigned long long (*acc)[kBatchClasses]) {
+    constexpr int C = kBatchClasses;
     constexpr int L = 8;
     // A vertical counter of L planes holds 2^L - 1 carries: chunks of at most
     // 2^L - 2 tiles leave room for the one masked tail tile.
@@ -392,13 +397,6 @@ batch_main(const ppc_desc* __restrict__ descs, const uint64_t* __restrict__ cum,
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int wpb = blockDim.x / kWave;
-    const uint64_t G = gridDim.x, b = blockIdx.x;
-    const uint64_t total = cum[m];
-    const uint64_t lo = share_lo(b, total, G), hi = share_lo(b + 1, total, G);
-    if (lo >= hi) return;  // whole block: no barrier is reached
-    __shared__ unsigned long long acc[kBatchMaxThreads / kWave][C];
-
-    uint32_t pos = first[b];
     uint64_t w0 = cum[pos], w1 = cum[pos + 1];
     for (; pos < m && w0 < hi; ++pos) {
         // the next position's bookkeeping is requested before this one is worked on
@@ -477,8 +475,69 @@ batch_main(const ppc_desc* __restrict__ descs, const uint64_t* __restrict__ cum,
     }
 }
 
+template <int LOGD>
+__global__ void __launch_bounds__(kBatchMaxThreads)
+batch_main(const ppc_desc* __restrict__ descs, const uint64_t* __restrict__ cum,
+           const uint32_t* __restrict__ first, uint64_t weight, unsigned long long* sink,
+           uint32_t m) {
+    const uint64_t G = gridDim.x, b = blockIdx.x;
+    const uint64_t total = cum[m];
+    const uint64_t lo = share_lo(b, total, G), hi = share_lo(b + 1, total, G);
+    if (lo >= hi) return;  // whole block: no barrier is reached
+    __shared__ unsigned long long acc[kBatchMaxThreads / kWave][kBatchClasses];
+    walk_share<LOGD>(descs, cum, first[b], m, lo, hi, weight, sink, b, acc);
+}
+
 static const void* main_kernel(int depth) {
     return depth == 32 ? (const void*)batch_main<5> : (const void*)batch_main<4>;
+}
+
+// Small batches in one kernel, for callers whose counters are already zero: every
+// block weighs all m <= kSmallBatch descriptors itself (the preparation of
+// batch_prep, redone per block from the same descriptors, so all blocks agree),
+// keeps the prefix array in LDS, finds its own first position and walks its share
+// as batch_main does.  No preparation kernel, and no gap between two kernels.
+constexpr uint32_t kSmallBatch = 1024;
+
+template <int LOGD>
+__global__ void __launch_bounds__(kBatchMaxThreads)
+batch_small(const ppc_desc* __restrict__ descs, uint32_t m, uint64_t weight) {
+    __shared__ uint64_t lcum[kSmallBatch + 1];
+    __shared__ uint64_t sh[kBatchMaxThreads / kWave];
+    __shared__ unsigned long long acc[kBatchMaxThreads / kWave][kBatchClasses];
+    const uint32_t T = blockDim.x, t = threadIdx.x;
+    const uint32_t R = (m + T - 1) / T;  // consecutive positions per thread
+    uint64_t local = 0;
+    uint32_t bad = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+        const uint32_t p = t * R + r;
+        if (p < m) {
+            const uint64_t w = weight_of(descs[stream_at(p, m)], weight, &bad);
+            lcum[p] = w;
+            local += w;
+        }
+    }
+    uint64_t total;
+    uint64_t run = block_exclusive_scan(local, &total, sh);  // barriers order the writes
+    for (uint32_t r = 0; r < R; ++r) {
+        const uint32_t p = t * R + r;
+        if (p < m) {
+            const uint64_t w = lcum[p];
+            lcum[p] = run;
+            run += w;
+        }
+    }
+    if (t == 0) lcum[m] = total;
+    __syncthreads();
+    const uint64_t G = gridDim.x, b = blockIdx.x;
+    const uint64_t lo = share_lo(b, total, G), hi = share_lo(b + 1, total, G);
+    if (lo >= hi) return;  // whole block: no barrier is reached
+    uint32_t l = 0, h = m;  // last position l < m with lcum[l] <= lo
+    while (h - l > 1) {
+        const uint32_t mid = l + (h - l) / 2;
+        if (lcum[mid] <= lo) l = mid; else h = mid;
+    }
+    walk_share<LOGD>(descs, (const uint64_t*)lcum, l, m, lo, hi, weight, nullptr, b, acc);
 }
 
 static int check_config(const ppc_batch_config& c) {
@@ -558,6 +617,25 @@ int batch_fresh(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s
         max_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 1u << 30);
     }
     return enqueue(pl, d_descs, m, s, nullptr, 1, max_blocks);
+}
+
+int batch_zeroed(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s,
+                 uint64_t bytes) {
+    if (!pl || !d_descs) return PPC_ERR_NULL;
+    if (m == 0) return PPC_OK;
+    if (m > pl->max_streams) return PPC_ERR_ARG;
+    if (m > kSmallBatch) return batch_fresh(pl, d_descs, m, s, bytes);
+    const ppc_batch_config& c = pl->cfg;
+    uint32_t G = (uint32_t)(c.blocks_per_cu * pl->cus);
+    const uint64_t units = (uint64_t)m * (uint64_t)c.stream_weight + bytes / 16;
+    const uint64_t per_block = kFreshUnitsPerWave * (uint64_t)(c.block_threads / kWave);
+    const uint64_t want = std::max<uint64_t>((units + per_block - 1) / per_block, 1);
+    if (want < G) G = (uint32_t)want;
+    uint64_t weight = (uint64_t)c.stream_weight;
+    void* args[] = {(void*)&d_descs, &m, &weight};
+    const void* kern = c.depth == 32 ? (const void*)batch_small<5> : (const void*)batch_small<4>;
+    PPC_HIP(hipLaunchKernel(kern, dim3(G), dim3(c.block_threads), args, 0, s));
+    return PPC_OK;
 }
 }  // namespace ppc
 

@@ -70,6 +70,12 @@ int launch_stream(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stre
 int batch_fresh(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, hipStream_t stream,
                 uint64_t bytes);
 
+// As batch_fresh for callers whose counters are zero already (the serving
+// executor clears them after reading them back): up to 1024 descriptors run as one
+// kernel that prepares its own shares, larger batches as batch_fresh.
+int batch_zeroed(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, hipStream_t stream,
+                 uint64_t bytes);
+
 int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has_edges,
                    uint64_t nbytes, Launch* out);
 

@@ -238,6 +238,9 @@ class HipExecutor : public Executor {
             s.stream = (int)(i % c.streams);
             PPC_HIP(hipMalloc(&s.d_meta, meta));
             PPC_HIP(hipMalloc(&s.d_counts, 256ull * c.max_batch));
+            // counters start at zero; each launch clears the ones it used after its
+            // results have been copied back (see launch)
+            PPC_HIP(hipMemset(s.d_counts, 0, 256ull * c.max_batch));
             PPC_HIP(hipHostMalloc(&s.h_meta, meta));
             PPC_HIP(hipHostMalloc(&s.h_counts, 256ull * c.max_batch));
             PPC_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
@@ -309,11 +312,14 @@ class HipExecutor : public Executor {
             void* args[] = {(void*)&d_segs, (void*)&n, &units};
             PPC_HIP(hipLaunchKernel((const void*)copy_segments, dim3(grid), dim3(256), args, 0, st));
         }
-        // counts are cleared by the batch's own prefix kernel
-        const int bst = batch_fresh(plans_[s.stream], s.d_descs(), n, st, bytes);
+        // the slot's counters are zero here (cleared after the slot's previous use)
+        const int bst = batch_zeroed(plans_[s.stream], s.d_descs(), n, st, bytes);
         if (bst) return bst;
         PPC_HIP(hipMemcpyAsync(s.h_counts, s.d_counts, 256ull * n, hipMemcpyDeviceToHost, st));
         PPC_HIP(hipEventRecord(s.done, st));
+        // Clear the counters used, for the slot's next launch on this same stream;
+        // enqueued after the event, so the results do not wait for it.
+        PPC_HIP(hipMemsetAsync(s.d_counts, 0, 256ull * n, st));
         s.busy = true;
         s.n = n;
         *handle = si;

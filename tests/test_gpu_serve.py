@@ -106,3 +106,27 @@ def test_unaligned_sources_are_copied_exactly(workload):
         exp = oracle_counts(pools.host[p][o:o + n * k // 8], n, k)
         assert comps["status"][j] == 0
         assert (comps["counts"][j][:k].astype(np.int64) == exp).all(), f"request {i} shift {shift[j]}"
+
+
+@pytest.mark.parametrize("in_place", [False, True], ids=["copy", "in_place"])
+def test_large_and_small_batches_share_slots(workload, in_place):
+    """Launches of more than 1024 requests (prepared in a kernel of their own) and of
+    fewer (one kernel that prepares its own shares) on the same two slots: every
+    launch must start from cleared counters, which the previous launch of the slot
+    cleared after its results were read back."""
+    trace, pools, reqs = workload
+    pick = np.nonzero(trace.nbytes < (1 << 18))[0][:2500]
+    r = reqs[pick].copy()
+    r["arrival"] = 0.0
+    say(f"serve: {len(pick)} requests at once, max_batch 1030, in_place={in_place}")
+    srv = S.Server(1 << 30, max_requests=4096, max_batch=1030, streams=1, in_place=in_place)
+    comps = srv.run_trace(r)
+    srv.close()
+    assert (comps["status"] == 0).all()
+    # 2120 requests in launches of at most 1030: two large ones fill both slots, the
+    # rest (fewer than 1024) reuses a slot after its counters were cleared
+    batches = np.unique(comps["batch"])
+    assert batches.max() > 1024 and batches.min() <= 1024 and len(pick) > 2 * 1030, batches
+    for j, i in enumerate(pick):
+        k = int(trace.ks[i])
+        assert (comps["counts"][j][:k].astype(np.int64) == expected(trace, pools, i)).all(), j
