@@ -379,9 +379,9 @@ prep_finish(uint32_t m, uint64_t* cum, const uint64_t* __restrict__ part,
 // ones, spread over many addresses).
 // The block's share [lo, hi) of the axis: every stream it touches, from position
 // pos on, counted into the stream's counters (or into sink).  cum: the prefix
-// array, in global memory or in LDS.
-template <int LOGD, typename Cum>
-__device__ __forceinline__ void walk_share(const ppc_desc* __restrict__ descs, Cum cum,
+// array, in global memory or in LDS; desc_at(pos): the descriptor at a position.
+template <int LOGD, typename Cum, typename DescAt>
+__device__ __forceinline__ void walk_share(DescAt desc_at, Cum cum,
                                            uint32_t pos, uint32_t m, uint64_t lo, uint64_t hi,
                                            uint64_t weight, unsigned long long* sink,
                                            uint64_t b,
@@ -402,7 +402,7 @@ __device__ __forceinline__ void walk_share(const ppc_desc* __restrict__ descs, C
         // the next position's bookkeeping is requested before this one is worked on
         const uint64_t w2 = pos + 2 <= m ? cum[pos + 2] : w1;
         if (w1 > lo && w1 > w0) {
-            const ppc_desc d = descs[stream_at(pos, m)];
+            const ppc_desc d = desc_at(pos);
             const int k = (int)d.k;
             const DevStream st = split_dev(d.ptr, d.n * (uint64_t)(k / 8), k);
             const uint64_t bw0 = w0 + weight;  // first body unit of the stream on the axis
@@ -485,7 +485,8 @@ batch_main(const ppc_desc* __restrict__ descs, const uint64_t* __restrict__ cum,
     const uint64_t lo = share_lo(b, total, G), hi = share_lo(b + 1, total, G);
     if (lo >= hi) return;  // whole block: no barrier is reached
     __shared__ unsigned long long acc[kBatchMaxThreads / kWave][kBatchClasses];
-    walk_share<LOGD>(descs, cum, first[b], m, lo, hi, weight, sink, b, acc);
+    walk_share<LOGD>([&](uint32_t pos) { return descs[stream_at(pos, m)]; }, cum, first[b], m,
+                     lo, hi, weight, sink, b, acc);
 }
 
 static const void* main_kernel(int depth) {
@@ -493,16 +494,18 @@ static const void* main_kernel(int depth) {
 }
 
 // Small batches in one kernel, for callers whose counters are already zero: every
-// block weighs all m <= kSmallBatch descriptors itself (the preparation of
-// batch_prep, redone per block from the same descriptors, so all blocks agree),
-// keeps the prefix array in LDS, finds its own first position and walks its share
-// as batch_main does.  No preparation kernel, and no gap between two kernels.
-constexpr uint32_t kSmallBatch = 1024;
+// block reads all m <= kSmallBatch descriptors into LDS and weighs them (the
+// preparation of batch_prep, redone per block from the same descriptors, so all
+// blocks agree), keeps the prefix array in LDS, finds its own first position and
+// walks its share as batch_main does.  No preparation kernel, and no gap between
+// two kernels.  The descriptors are read once per block, so they may live in
+// pinned host memory (the serving executor's staging buffer).
 
 template <int LOGD>
 __global__ void __launch_bounds__(kBatchMaxThreads)
 batch_small(const ppc_desc* __restrict__ descs, uint32_t m, uint64_t weight) {
     __shared__ uint64_t lcum[kSmallBatch + 1];
+    __shared__ ppc_desc ldesc[kSmallBatch];  // position order
     __shared__ uint64_t sh[kBatchMaxThreads / kWave];
     __shared__ unsigned long long acc[kBatchMaxThreads / kWave][kBatchClasses];
     const uint32_t T = blockDim.x, t = threadIdx.x;
@@ -512,7 +515,9 @@ batch_small(const ppc_desc* __restrict__ descs, uint32_t m, uint64_t weight) {
     for (uint32_t r = 0; r < R; ++r) {
         const uint32_t p = t * R + r;
         if (p < m) {
-            const uint64_t w = weight_of(descs[stream_at(p, m)], weight, &bad);
+            const ppc_desc d = descs[stream_at(p, m)];
+            ldesc[p] = d;
+            const uint64_t w = weight_of(d, weight, &bad);
             lcum[p] = w;
             local += w;
         }
@@ -537,7 +542,8 @@ batch_small(const ppc_desc* __restrict__ descs, uint32_t m, uint64_t weight) {
         const uint32_t mid = l + (h - l) / 2;
         if (lcum[mid] <= lo) l = mid; else h = mid;
     }
-    walk_share<LOGD>(descs, (const uint64_t*)lcum, l, m, lo, hi, weight, nullptr, b, acc);
+    walk_share<LOGD>([&](uint32_t pos) { return ldesc[pos]; }, (const uint64_t*)lcum, l, m, lo,
+                     hi, weight, nullptr, b, acc);
 }
 
 static int check_config(const ppc_batch_config& c) {
@@ -622,6 +628,7 @@ int batch_fresh(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s
 int batch_zeroed(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s,
                  uint64_t bytes) {
     if (!pl || !d_descs) return PPC_ERR_NULL;
+    // (m <= kSmallBatch: d_descs may be pinned host memory, read once per block)
     if (m == 0) return PPC_OK;
     if (m > pl->max_streams) return PPC_ERR_ARG;
     if (m > kSmallBatch) return batch_fresh(pl, d_descs, m, s, bytes);

@@ -71,9 +71,11 @@ int batch_fresh(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, hipStream_t
                 uint64_t bytes);
 
 // As batch_fresh for callers whose counters are zero already (the serving
-// executor clears them after reading them back): up to 1024 descriptors run as one
-// kernel that prepares its own shares, larger batches as batch_fresh.
-int batch_zeroed(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, hipStream_t stream,
+// executor clears them after reading them back): up to kSmallBatch descriptors run
+// as one kernel that prepares its own shares, larger batches as batch_fresh.  Up to
+// kSmallBatch, descs may also be pinned host memory (each block reads them once).
+constexpr uint32_t kSmallBatch = 1024;
+int batch_zeroed(ppc_plan* plan, const ppc_desc* descs, uint32_t m, hipStream_t stream,
                  uint64_t bytes);
 
 int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has_edges,

@@ -241,7 +241,12 @@ class HipExecutor : public Executor {
             // counters start at zero; each launch clears the ones it used after its
             // results have been copied back (see launch)
             PPC_HIP(hipMemset(s.d_counts, 0, 256ull * c.max_batch));
-            PPC_HIP(hipHostMalloc(&s.h_meta, meta));
+            // In place, batches of up to kSmallBatch requests are read by the counting
+            // kernel straight from this pinned buffer, which the host rewrites before
+            // every launch of the slot: fine-grained (coherent) memory, so that the
+            // device never holds a stale copy of it.
+            PPC_HIP(hipHostMalloc(&s.h_meta, meta,
+                                  in_place_ ? hipHostMallocCoherent : hipHostMallocDefault));
             PPC_HIP(hipHostMalloc(&s.h_counts, 256ull * c.max_batch));
             PPC_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
         }
@@ -301,9 +306,15 @@ class HipExecutor : public Executor {
                               s.d_counts + 32ull * i};
             bytes += a.bytes;
         }
-        // one copy of the descriptors (and the copy segments right after them)
-        const size_t meta = in_place_ ? sizeof(ppc_desc) * n : seg_off + sizeof(CopySeg) * n;
-        PPC_HIP(hipMemcpyAsync(s.d_meta, s.h_meta, meta, hipMemcpyHostToDevice, st));
+        // One copy of the descriptors (and the copy segments right after them), except
+        // in place for up to kSmallBatch requests: the counting kernel then reads the
+        // descriptors from the pinned buffer itself, which saves the copy and the
+        // queue's gap after it.
+        const bool direct = in_place_ && n <= kSmallBatch;
+        if (!direct) {
+            const size_t meta = in_place_ ? sizeof(ppc_desc) * n : seg_off + sizeof(CopySeg) * n;
+            PPC_HIP(hipMemcpyAsync(s.d_meta, s.h_meta, meta, hipMemcpyHostToDevice, st));
+        }
         if (units) {
             const CopySeg* d_segs = (const CopySeg*)(s.d_meta + seg_off);
             // about 16 KiB per block, at most 8 blocks per compute unit
@@ -313,7 +324,8 @@ class HipExecutor : public Executor {
             PPC_HIP(hipLaunchKernel((const void*)copy_segments, dim3(grid), dim3(256), args, 0, st));
         }
         // the slot's counters are zero here (cleared after the slot's previous use)
-        const int bst = batch_zeroed(plans_[s.stream], s.d_descs(), n, st, bytes);
+        const int bst =
+            batch_zeroed(plans_[s.stream], direct ? s.h_descs() : s.d_descs(), n, st, bytes);
         if (bst) return bst;
         PPC_HIP(hipMemcpyAsync(s.h_counts, s.d_counts, 256ull * n, hipMemcpyDeviceToHost, st));
         PPC_HIP(hipEventRecord(s.done, st));
