@@ -6,10 +6,11 @@
 // the encoded stream is the frequency histogram.  Here each lane loads raw ids
 // (u8 or u16) with the same nontemporal dwordx4 tiles as the counting kernel,
 // turns them into packed one-hot codes in registers (see Codes: four 8-bit, two
-// 16-bit or one 32-bit code per dword; ids >= bins have no code and are tallied
-// apart), and feeds the code dwords of a tile to one Harley-Seal circuit of
-// Sec. 2, whose carry enters the cross-tile levels of ppc_tree.h before it is
-// counted per category class as in the counting kernel.
+// 16-bit or one 32-bit code per dword; ids >= bins have no code), and feeds the
+// code dwords of a tile to one Harley-Seal circuit of Sec. 2, whose carry enters
+// the cross-tile levels of ppc_tree.h before it is counted per category class as
+// in the counting kernel.  Every id with a code adds one to exactly one class, so
+// the ids >= bins are the ids a lane saw less the sum of its class totals.
 // Head and tail ids outside the 16-byte aligned body are expanded one per lane by
 // the first wave; padding never becomes an id.
 #include "ppc_device.h"
@@ -38,15 +39,98 @@ struct Codes {
     // Input bits that are zero in every input dword whose ids are all < C.
     static constexpr uint32_t BAD = LANE * (IDMASK & ~(uint32_t)(C - 1));
 
-    // Lanes of ids >= C, all ones per such id; *count receives how many there are.
-    // Per lane the high id bits, moved down, are at most 31 (bytes) or 0x1FFF
-    // (halves), so adding 0x7F / 0x7FFF sets the lane's top bit exactly for a
-    // nonzero value and never carries into the next lane.
-    __device__ static __forceinline__ uint32_t dead_ids(uint32_t x, uint32_t* count) {
+    // Lanes of ids >= C, all ones per such id.  Per lane the high id bits, moved
+    // down, are at most 31 (bytes) or 0x1FFF (halves), so adding 0x7F / 0x7FFF
+    // sets the lane's top bit exactly for a nonzero value and never carries into
+    // the next lane.
+    __device__ static __forceinline__ uint32_t dead_ids(uint32_t x) {
         const uint32_t top = IDB == 1 ? 0x80808080u : 0x80008000u;
         const uint32_t z = (((x & BAD) >> LOGC) + (top - LANE)) & top;
-        *count = __builtin_popcount(z);
         return z | (z - (z >> (IDB == 1 ? 7 : 15)));
+    }
+
+    // The masked path: a tile that may hold ids >= C, or dwords that are not
+    // input (unit[i] false: the missing units of a partial tile).  Those ids must
+    // add nothing to the classes.  u16 ids with C = 16, 32 get no code (dead_ids,
+    // make<true>).  Otherwise some get a stand-in code that take_back() later
+    // removes, *ph counting the stand-ins:
+    // - C = 8 (make_masked): the byte table of make() applied to the raw ids (u8)
+    //   or to their low bytes (u16).  Selectors 8..11 copy the sign of table
+    //   bytes 1, 3, 5, 7 (0x02, 0x08, 0x20: zero; 0x80: 0xFF), 12 gives zero and
+    //   13..255 give 0xFF, so a byte of the result is a one-hot code (one bit) or
+    //   an id >= 8 (0x00, or 0xFF: one in every class).  A u16 id whose high byte
+    //   is not zero is cleared by the mask table below applied to its high byte.
+    //   Bits 0 and 1 both set mark exactly the 0xFF bytes; *ph counts them.
+    // - C = 16, 32 (clear_ids, then make<false>): a byte table gives each id a
+    //   mask byte, 0x00 for ids < C and 0xFF otherwise (table {0xFFFFFFFF :
+    //   0xFFFFFF00}, indexed by the id's bits above LOGC: bits 5..7 for C = 32;
+    //   bits 4..7 for C = 16, with bit 3 of the index also set in bit 0 so that
+    //   selector 12, which gives zero, never occurs and 8..11 copy the sign of a
+    //   0xFF byte).
+    //   Masked ids become id 0 in place, whose code lands in class 0; *ph adds
+    //   the mask's popcount, 8 per such id.
+    static constexpr bool CLEARS_IDS = IDB == 1 && C != 8;
+
+    __device__ static __forceinline__ void make_masked(uint32_t* code, const uint32_t* in,
+                                                       const bool* unit, uint32_t* ph) {
+        static_assert(!CLEARS_IDS, "u8 ids with C = 16, 32 go through clear_ids");
+        if constexpr (C == 8 && IDB == 1) {
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) {
+                const uint32_t raw = __builtin_amdgcn_perm(0x80402010u, 0x08040201u, in[i]);
+                const uint32_t ff = raw & (raw >> 1) & 0x01010101u;
+                code[i] = unit[i] ? raw : 0u;
+                *ph += unit[i] ? (uint32_t)__builtin_popcount(ff) : 0u;
+            }
+        } else if constexpr (C == 8) {
+#pragma unroll
+            for (int i = 0; i < NIN / 2; ++i) {
+                const uint32_t lo = in[2 * i], hi = in[2 * i + 1];
+                // low and high bytes of the four ids
+                const uint32_t lb = __builtin_amdgcn_perm(hi, lo, 0x06040200u);
+                const uint32_t hb = __builtin_amdgcn_perm(hi, lo, 0x07050301u);
+                const uint32_t mh =
+                    __builtin_amdgcn_perm(0xFFFFFFFFu, 0xFFFFFF00u, hb | ((hb >> 3) & 0x01010101u));
+                const uint32_t c = __builtin_amdgcn_perm(0x80402010u, 0x08040201u, lb) & ~mh;
+                const uint32_t ff = c & (c >> 1) & 0x01010101u;
+                // both dwords of a pair lie in one 16-byte unit
+                code[i] = unit[2 * i] ? c : 0u;
+                *ph += unit[2 * i] ? (uint32_t)__builtin_popcount(ff) : 0u;
+            }
+        } else {
+            uint32_t dead[NIN];
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) dead[i] = unit[i] ? dead_ids(in[i]) : 0xFFFFFFFFu;
+            make<true>(code, in, dead);
+        }
+    }
+
+    __device__ static __forceinline__ void clear_ids(uint32_t* in, const bool* unit,
+                                                     uint32_t* ph) {
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+            uint32_t sel;
+            if constexpr (C == 32) {
+                sel = (in[i] >> 5) & 0x07070707u;
+            } else {
+                const uint32_t h = (in[i] >> 4) & 0x0F0F0F0Fu;
+                sel = h | ((h >> 3) & 0x01010101u);
+            }
+            const uint32_t m =
+                unit[i] ? __builtin_amdgcn_perm(0xFFFFFFFFu, 0xFFFFFF00u, sel) : 0xFFFFFFFFu;
+            *ph += (uint32_t)__builtin_popcount(m);
+            in[i] &= ~m;
+        }
+    }
+
+    // Removes from a lane's class totals what the stand-in codes added.
+    __device__ static __forceinline__ void take_back(uint32_t (&tot)[C], uint32_t ph) {
+        if constexpr (C == 8) {
+#pragma unroll
+            for (int i = 0; i < C; ++i) tot[i] -= ph;
+        } else if constexpr (IDB == 1) {
+            tot[0] -= ph / 8;
+        }
     }
 
     // Code dwords of NIN input dwords; dead[i] marks ids of in[i] that get no code.
@@ -55,24 +139,30 @@ struct Codes {
     // byte j, and selector 0x0C yields zero, which is what a dead id is mapped to).
     // C = 16: packed 16-bit shifts, two codes per op, dead halves masked.  C = 32:
     // one byte- or word-selecting shift per id, dead ids masked.
+    // With MASKED false every id is known to be below C (dead is not read): the same
+    // codes without the masking, which is most of the arithmetic for C = 32.
+    template <bool MASKED>
     __device__ static __forceinline__ void make(uint32_t* code, const uint32_t* in,
                                                 const uint32_t* dead) {
         // Dead ids are zeroed first, so that every shift amount below is in range;
         // the code each of them then gets is cleared again.
-        uint32_t live[NIN];
+        uint32_t live[NIN], dd[NIN];
 #pragma unroll
-        for (int i = 0; i < NIN; ++i) live[i] = in[i] & ~dead[i];
+        for (int i = 0; i < NIN; ++i) {
+            dd[i] = MASKED ? dead[i] : 0u;
+            live[i] = in[i] & ~dd[i];
+        }
         if constexpr (C == 8) {
             if constexpr (IDB == 1) {
 #pragma unroll
                 for (int i = 0; i < NIN; ++i)
                     code[i] = __builtin_amdgcn_perm(0x80402010u, 0x08040201u,
-                                                    live[i] | (dead[i] & 0x0C0C0C0Cu));
+                                                    live[i] | (dd[i] & 0x0C0C0C0Cu));
             } else {
 #pragma unroll
                 for (int i = 0; i < NIN / 2; ++i) {
-                    const uint32_t lo = live[2 * i] | (dead[2 * i] & 0x000C000Cu);
-                    const uint32_t hi = live[2 * i + 1] | (dead[2 * i + 1] & 0x000C000Cu);
+                    const uint32_t lo = live[2 * i] | (dd[2 * i] & 0x000C000Cu);
+                    const uint32_t hi = live[2 * i + 1] | (dd[2 * i + 1] & 0x000C000Cu);
                     // the four id bytes, then the table lookup
                     const uint32_t sel = __builtin_amdgcn_perm(hi, lo, 0x06040200u);
                     code[i] = __builtin_amdgcn_perm(0x80402010u, 0x08040201u, sel);
@@ -87,8 +177,8 @@ struct Codes {
                     // ids 0 and 1 (2 and 3) widened to the two 16-bit shift amounts
                     const uint32_t a = __builtin_amdgcn_perm(0u, live[i], 0x0C010C00u);
                     const uint32_t b = __builtin_amdgcn_perm(0u, live[i], 0x0C030C02u);
-                    const uint32_t da = __builtin_amdgcn_perm(0u, dead[i], 0x01010000u);
-                    const uint32_t db = __builtin_amdgcn_perm(0u, dead[i], 0x03030202u);
+                    const uint32_t da = __builtin_amdgcn_perm(0u, dd[i], 0x01010000u);
+                    const uint32_t db = __builtin_amdgcn_perm(0u, dd[i], 0x03030202u);
                     code[2 * i] =
                         __builtin_bit_cast(uint32_t, one << __builtin_bit_cast(u16x2, a)) & ~da;
                     code[2 * i + 1] =
@@ -98,7 +188,7 @@ struct Codes {
 #pragma unroll
                 for (int i = 0; i < NIN; ++i)
                     code[i] = __builtin_bit_cast(uint32_t, one << __builtin_bit_cast(u16x2, live[i])) &
-                              ~dead[i];
+                              ~dd[i];
             }
         } else {
 #pragma unroll
@@ -107,7 +197,7 @@ struct Codes {
                 for (int j = 0; j < IDS_PER_IN; ++j) {
                     const int sh = 32 / IDS_PER_IN * j;
                     const uint32_t keep =
-                        ~(uint32_t)__builtin_amdgcn_sbfe((int)dead[i], sh, 32 / IDS_PER_IN);
+                        ~(uint32_t)__builtin_amdgcn_sbfe((int)dd[i], sh, 32 / IDS_PER_IN);
                     code[i * IDS_PER_IN + j] = (1u << ((live[i] >> sh) & IDMASK)) & keep;
                 }
             }
@@ -116,7 +206,7 @@ struct Codes {
 };
 
 template <int C, int IDB, int LOGD>
-__device__ __forceinline__ uint32_t onehot_step(uint32_t (&B)[LOGD], uint32_t& other,
+__device__ __forceinline__ uint32_t onehot_step(uint32_t (&B)[LOGD], uint32_t& ph,
                                                 const u32x4 (&v)[4], const bool (&valid)[4],
                                                 bool maybe_partial) {
     using K = Codes<C, IDB>;
@@ -133,31 +223,42 @@ __device__ __forceinline__ uint32_t onehot_step(uint32_t (&B)[LOGD], uint32_t& o
 #pragma unroll
     for (int i = 0; i < K::NIN; ++i) any |= in[i];
     const uint32_t bad = any & K::BAD;
-    uint32_t code[K::NCODE], dead[K::NIN];
+    uint32_t code[K::NCODE];
     // Wave-uniform choice: ids are masked only when some lane holds an id >= C or
     // the tile is the partial last one (whose missing units carry no ids at all).
-    if (!maybe_partial && __ballot(bad != 0) == 0) {
+    const bool clean = !maybe_partial && __ballot(bad != 0) == 0;
+    bool unit[K::NIN];
 #pragma unroll
-        for (int i = 0; i < K::NIN; ++i) dead[i] = 0;
-    } else {
-#pragma unroll
-        for (int i = 0; i < K::NIN; ++i) {
-            uint32_t n = 0;
-            const uint32_t d = K::dead_ids(in[i], &n);
-            const bool unit = valid[i / 4];
-            dead[i] = unit ? d : 0xFFFFFFFFu;
-            other += unit ? n : 0u;
-        }
+    for (int i = 0; i < K::NIN; ++i) unit[i] = valid[i / 4];
+    // Each branch runs its own copy of the circuit, so that no code or id is live
+    // across the join (a value merged there costs a register copy per id on the
+    // fast path).
+    if (clean) {
+        K::template make<false>(code, in, nullptr);
+        return Circuit<LOGD>::run(B, code);
     }
-    K::make(code, in, dead);
-    return Circuit<LOGD>::run(B, code);
+    if constexpr (K::CLEARS_IDS) {
+        // The same codes as the fast path once the ids are cleared, fed to the
+        // circuit in reverse order so that the compiler does not merge the two
+        // branches' code: the circuit keeps every class's weighted sum whatever
+        // the order of its inputs.
+        K::clear_ids(in, unit, &ph);
+        K::template make<false>(code, in, nullptr);
+        uint32_t rev[K::NCODE];
+#pragma unroll
+        for (int i = 0; i < K::NCODE; ++i) rev[i] = code[K::NCODE - 1 - i];
+        return Circuit<LOGD>::run(B, rev);
+    } else {
+        K::make_masked(code, in, unit, &ph);
+        return Circuit<LOGD>::run(B, code);
+    }
 }
 
 // The id at head or tail position `lane` of the first wave: lanes 0..15 take
 // head ids, lanes 16..31 tail ids.  u16 ids are 2-byte aligned, so the head and
-// tail hold whole ids.
+// tail hold whole ids.  `seen` counts the id.
 template <int C, int IDB>
-__device__ __forceinline__ uint32_t edge_onehot(const Edges& e, int lane, uint32_t& other) {
+__device__ __forceinline__ uint32_t edge_onehot(const Edges& e, int lane, uint32_t& seen) {
     const uint8_t* p = nullptr;
     if (lane < 16) {
         if ((uint32_t)(lane * IDB) < e.head_len) p = e.head + lane * IDB;
@@ -166,9 +267,8 @@ __device__ __forceinline__ uint32_t edge_onehot(const Edges& e, int lane, uint32
     }
     if (!p) return 0u;
     const uint32_t id = IDB == 1 ? (uint32_t)p[0] : (uint32_t)p[0] | ((uint32_t)p[1] << 8);
-    if (id < (uint32_t)C) return 1u << id;
-    ++other;
-    return 0u;
+    ++seen;
+    return id < (uint32_t)C ? 1u << id : 0u;
 }
 
 template <int C, int IDB>
@@ -188,28 +288,37 @@ onehot_kernel(const u32x4* __restrict__ body, uint64_t units, Edges edges,
 
     // Levels past the tile: more for wider codes, whose per-class count costs more.
     constexpr int E = C == 8 ? 1 : C == 16 ? 2 : 3;
-    uint32_t B[LOGD], other = 0;
+    // ph: stand-in codes of the masked path (Codes::make_masked)
+    uint32_t B[LOGD], ph = 0;
 #pragma unroll
     for (int j = 0; j < LOGD; ++j) B[j] = 0;
     TileTree<C, LOGD, E> tree;
     tree.init();
     const bool all[U] = {true, true, true, true};
     walk_tiles<U>(body, full, gw, nw, lane, [&](const u32x4(&v)[U]) {
-        tree.add(onehot_step<C, IDB, LOGD>(B, other, v, all, false));
+        tree.add(onehot_step<C, IDB, LOGD>(B, ph, v, all, false));
     });
+    // ids this lane has seen: 4 / IDB per input dword, 16 dwords per tile
+    uint32_t seen = tree.tiles * (16u * 4u / IDB);
     const uint64_t rem = units - full * TILE;
     if (rem != 0 && gw == full % nw) {
         u32x4 t[U];
         load_tile_masked<U>(t, body + full * TILE + lane, lane, rem);
         bool valid[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) valid[j] = (uint64_t)(j * kWave + lane) < rem;
-        tree.add(onehot_step<C, IDB, LOGD>(B, other, t, valid, true));
+        for (int j = 0; j < U; ++j) {
+            valid[j] = (uint64_t)(j * kWave + lane) < rem;
+            seen += valid[j] ? 4u * 4u / IDB : 0u;
+        }
+        tree.add(onehot_step<C, IDB, LOGD>(B, ph, t, valid, true));
     }
-    const uint32_t e = (blockIdx.x == 0 && wave == 0) ? edge_onehot<C, IDB>(edges, lane, other) : 0u;
+    const uint32_t e = (blockIdx.x == 0 && wave == 0) ? edge_onehot<C, IDB>(edges, lane, seen) : 0u;
 
-    uint32_t tot[C];
+    uint32_t tot[C], other = seen;
     tree.totals(tot, B, e);
+    Codes<C, IDB>::take_back(tot, ph);
+#pragma unroll
+    for (int i = 0; i < C; ++i) other -= tot[i];
     const uint32_t v = wave_reduce_scatter<C>(tot, lane);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) other += (uint32_t)__shfl_xor((int)other, o, kWave);
@@ -237,19 +346,17 @@ static const void* onehot_of(int bins, int id_bytes) {
     return (const void*)table[id_bytes - 1][bins == 8 ? 0 : bins == 16 ? 1 : 2];
 }
 
-// Default launch shape per (categories, id width), the fastest of a sweep of block
-// sizes 64..256 and 1..12 blocks per CU over 16 GiB of ids on MI355X.  All of them
-// keep more waves resident than the counting kernel: each id costs an expansion on
-// top of its share of the circuit, so there is more arithmetic to overlap with the
-// loads, most of all for 32 categories of u8 ids (one 32-bit code per id).
+// Default launch shape per (categories, id width), from a sweep of block sizes 64..256
+// and 1..12 blocks per CU over 16 GiB of ids on MI355X.  Few waves win, as for the
+// counting kernel: three per CU for 8 categories, whose codes cost one op per four
+// u8 ids, and four (one per SIMD) where a tile costs more arithmetic (16 or 32
+// categories, or ids outside the categories, which take the masked path).
 struct OnehotShape {
     int threads, blocks_per_cu;
 };
 
-static OnehotShape onehot_shape(int bins, int id_bytes) {
-    if (id_bytes == 1) return bins == 8 ? OnehotShape{256, 2} : bins == 16 ? OnehotShape{64, 8}
-                                                                           : OnehotShape{256, 8};
-    return bins == 32 ? OnehotShape{64, 6} : OnehotShape{256, 2};
+static OnehotShape onehot_shape(int bins) {
+    return bins == 8 ? OnehotShape{64, 3} : OnehotShape{256, 1};
 }
 
 static int launch_histogram(const void* ids, uint64_t n, int id_bytes, int bins,
@@ -269,7 +376,7 @@ static int launch_histogram(const void* ids, uint64_t n, int id_bytes, int bins,
     ppc_launch_config c = {};
     if (cfg) c = *cfg;
     if (c.variant != PPC_VARIANT_CSA || (c.depth != 0)) return PPC_ERR_ARG;
-    const OnehotShape dflt = onehot_shape(bins, id_bytes);
+    const OnehotShape dflt = onehot_shape(bins);
     const int threads = c.block_threads ? c.block_threads : dflt.threads;
     if (threads < kWave || threads > kOnehotThreads || threads % kWave) return PPC_ERR_ARG;
     if (c.blocks_per_cu < 0 || c.grid < 0) return PPC_ERR_ARG;

@@ -90,3 +90,31 @@ def test_histogram_rare_wide_invalid(id_bytes, bins):
         buf, o = to_device(host, off)
         got = counts_np(api.histogram(buf, bins, id_bytes=id_bytes, n=n, byte_offset=o))
         assert (got == exp).all(), (id_bytes, bins, off)
+
+
+@pytest.mark.parametrize("bins", [8, 16, 32])
+def test_constant_ids_closed_form(bins):
+    """Every u8 id value, and u16 values around each boundary, as a constant stream
+    with a ragged length and an unaligned start.  Closed form: all n ids fall in the
+    one class of the id, or all outside the categories.  For u8 ids and 8 categories
+    this covers every byte-table form an id >= 8 takes (no code, or a code in every
+    class that is taken back)."""
+    n = 70_001
+    buf = torch.empty(2 * n + 16, dtype=torch.uint8, device="cuda")
+    for v in range(256):
+        buf.fill_(v)
+        got = counts_np(api.histogram(buf, bins, n=n, byte_offset=3))
+        exp = np.zeros(bins + 1, np.int64)
+        exp[min(v, bins)] = n
+        assert (got == exp).all(), ("u8", bins, v, got)
+    say(f"constant u8 ids bins={bins}: 256 values")
+    # around each boundary, plus high bytes 8..12 over valid low bytes (for 8
+    # categories a high byte of 12 is the selector the mask table must not meet)
+    extra = [11, 12, 13, 255, 256, 257, 0x0800 | 2, 0x0B00 | 1, 0x0C00, 0x0C00 | 5, 0x0D00,
+             0x7FFF, 0x8000, 0x8000 | 3, 0xFFFF]
+    for v in list(range(bins + 2)) + extra:
+        buf.view(torch.int16)[: n + 8].fill_(v - 65536 if v >= 32768 else v)
+        got = counts_np(api.histogram(buf, bins, id_bytes=2, n=n, byte_offset=2))
+        exp = np.zeros(bins + 1, np.int64)
+        exp[min(v, bins)] = n
+        assert (got == exp).all(), ("u16", bins, v, got)
