@@ -231,7 +231,10 @@ int pospopcnt_batch(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, ppc_str
 /* Times candidate configurations on the given workload (counts are redirected
  * to plan scratch, so the descriptors' counters are not touched), keeps the
  * fastest in the plan and returns its time per call in *best_ms (may be NULL).
- * Synchronises `stream`. */
+ * Every candidate (56 shapes of depth, block size, blocks per CU and stream
+ * weight) is timed 3 times; the 4 with the lowest medians are then timed 5
+ * times more, in turn, and the lowest median of those decides.  Synchronises
+ * `stream`; on an error the plan keeps its previous configuration. */
 int ppc_plan_autotune(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, ppc_stream stream,
                       float* best_ms);
 
