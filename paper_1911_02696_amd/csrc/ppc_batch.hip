@@ -626,6 +626,15 @@ int batch_fresh(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s
     return enqueue(pl, d_descs, m, s, nullptr, 1, max_blocks);
 }
 
+uint32_t small_batch_grid(const ppc_plan* pl, uint32_t m, uint64_t bytes) {
+    const ppc_batch_config& c = pl->cfg;
+    const uint32_t g = (uint32_t)(c.blocks_per_cu * pl->cus);
+    const uint64_t units = (uint64_t)m * (uint64_t)c.stream_weight + bytes / 16;
+    const uint64_t per_block = kFreshUnitsPerWave * (uint64_t)(c.block_threads / kWave);
+    const uint64_t want = std::max<uint64_t>((units + per_block - 1) / per_block, 1);
+    return want < g ? (uint32_t)want : g;
+}
+
 int batch_zeroed(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s,
                  uint64_t bytes) {
     if (!pl || !d_descs) return PPC_ERR_NULL;
@@ -634,11 +643,7 @@ int batch_zeroed(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t 
     if (m > pl->max_streams) return PPC_ERR_ARG;
     if (m > kSmallBatch) return batch_fresh(pl, d_descs, m, s, bytes);
     const ppc_batch_config& c = pl->cfg;
-    uint32_t G = (uint32_t)(c.blocks_per_cu * pl->cus);
-    const uint64_t units = (uint64_t)m * (uint64_t)c.stream_weight + bytes / 16;
-    const uint64_t per_block = kFreshUnitsPerWave * (uint64_t)(c.block_threads / kWave);
-    const uint64_t want = std::max<uint64_t>((units + per_block - 1) / per_block, 1);
-    if (want < G) G = (uint32_t)want;
+    const uint32_t G = small_batch_grid(pl, m, bytes);
     uint64_t weight = (uint64_t)c.stream_weight;
     void* args[] = {(void*)&d_descs, &m, &weight};
     const void* kern = c.depth == 32 ? (const void*)batch_small<5> : (const void*)batch_small<4>;

@@ -77,6 +77,11 @@ int batch_fresh(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, hipStream_t
 constexpr uint32_t kSmallBatch = 1024;
 int batch_zeroed(ppc_plan* plan, const ppc_desc* descs, uint32_t m, hipStream_t stream,
                  uint64_t bytes);
+// The grid batch_zeroed launches for m <= kSmallBatch descriptors and `bytes` of input.
+uint32_t small_batch_grid(const ppc_plan* plan, uint32_t m, uint64_t bytes);
+// Descriptors a launch may read from pinned host memory, summed over its blocks,
+// before one small host-to-device copy is the cheaper way.
+constexpr uint64_t kDirectReads = 2048;
 
 int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has_edges,
                    uint64_t nbytes, Launch* out);

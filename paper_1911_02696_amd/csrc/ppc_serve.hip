@@ -241,10 +241,10 @@ class HipExecutor : public Executor {
             // counters start at zero; each launch clears the ones it used after its
             // results have been copied back (see launch)
             PPC_HIP(hipMemset(s.d_counts, 0, 256ull * c.max_batch));
-            // In place, batches of up to kSmallBatch requests are read by the counting
-            // kernel straight from this pinned buffer, which the host rewrites before
-            // every launch of the slot: fine-grained (coherent) memory, so that the
-            // device never holds a stale copy of it.
+            // In place, small launches are read by the counting kernel straight from
+            // this pinned buffer (see launch), which the host rewrites before every
+            // launch of the slot: fine-grained (coherent) memory, so that the device
+            // never holds a stale copy of it.
             PPC_HIP(hipHostMalloc(&s.h_meta, meta,
                                   in_place_ ? hipHostMallocCoherent : hipHostMallocDefault));
             PPC_HIP(hipHostMalloc(&s.h_counts, 256ull * c.max_batch));
@@ -307,10 +307,12 @@ class HipExecutor : public Executor {
             bytes += a.bytes;
         }
         // One copy of the descriptors (and the copy segments right after them), except
-        // in place for up to kSmallBatch requests: the counting kernel then reads the
-        // descriptors from the pinned buffer itself, which saves the copy and the
-        // queue's gap after it.
-        const bool direct = in_place_ && n <= kSmallBatch;
+        // in place for launches small enough for the counting kernel to read the
+        // descriptors from the pinned buffer itself, every block once (kDirectReads
+        // descriptors in all at most): that saves the copy and the queue's gap after it.
+        const bool direct =
+            in_place_ && n <= kSmallBatch &&
+            (uint64_t)small_batch_grid(plans_[s.stream], n, bytes) * n <= kDirectReads;
         if (!direct) {
             const size_t meta = in_place_ ? sizeof(ppc_desc) * n : seg_off + sizeof(CopySeg) * n;
             PPC_HIP(hipMemcpyAsync(s.d_meta, s.h_meta, meta, hipMemcpyHostToDevice, st));
