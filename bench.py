@@ -412,7 +412,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
-    ap.add_argument("--variant", default="csa", choices=["csa", "ballot"])
+    ap.add_argument("--variant", default="csa", choices=["csa", "ballot", "hybrid"])
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
@@ -596,7 +596,7 @@ def main():
 
     achieved = nbytes / avg_kernel / 1e9
     src_hash = kernel_source_hash()
-    kname = {"csa": "csa_kernel", "ballot": "ballot_kernel"}[args.variant]
+    kname = {"csa": "csa_kernel", "ballot": "ballot_kernel", "hybrid": "hybrid_kernel"}[args.variant]
     traffic = read_traffic(args.variant, args.workload, src_hash, nbytes)
     value = nbytes / (wall / args.steps) / 1e9
     line = {

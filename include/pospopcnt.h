@@ -86,14 +86,17 @@ int pospopcnt(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stream s
 /* Kernel variants. */
 enum {
     PPC_VARIANT_CSA = 0,     /* per-lane Harley-Seal circuit + masked popcount (Sec. 4.1) */
-    PPC_VARIANT_BALLOT = 1   /* wave-wide bit transposition: ballot per bit, popcount */
+    PPC_VARIANT_BALLOT = 1,  /* wave-wide bit transposition: ballot per bit, popcount */
+    PPC_VARIANT_HYBRID = 2   /* the CSA circuit, its carry planes counted by the ballot
+                                transposition instead of per-lane class counters */
 };
 
 /* Launch configuration for pospopcnt_ex.  Zero in any field selects the
  * library's default for that field. */
 typedef struct {
-    int32_t variant;        /* PPC_VARIANT_CSA or PPC_VARIANT_BALLOT (k <= 32 only) */
-    int32_t depth;          /* CSA: inputs per lane per circuit, 8, 16 or 32 dwords
+    int32_t variant;        /* PPC_VARIANT_CSA, or PPC_VARIANT_BALLOT or _HYBRID (k <= 32
+                               only) */
+    int32_t depth;          /* CSA, HYBRID: inputs per lane per circuit, 8, 16 or 32 dwords
                                (the 2^N-input circuits of Sec. 2; the paper's 256 B /
                                512 B / 1 kB circuits are N = 2, 3, 4) */
     int32_t block_threads;  /* 64 .. 256, multiple of 64 */

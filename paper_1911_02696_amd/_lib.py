@@ -18,7 +18,7 @@ STATUS_NAMES = {
     4: "PPC_ERR_RANGE", 5: "PPC_ERR_HIP", 6: "PPC_ERR_BUDGET", 7: "PPC_ERR_ARG",
     8: "PPC_ERR_OVERLAP", 9: "PPC_ERR_STATE",
 }
-VARIANT_CSA, VARIANT_BALLOT = 0, 1
+VARIANT_CSA, VARIANT_BALLOT, VARIANT_HYBRID = 0, 1, 2
 
 
 class PpcError(RuntimeError):

@@ -13,7 +13,7 @@ import torch
 from . import _lib as L
 from ._lib import LaunchConfig, PpcError, check
 
-VARIANTS = {"csa": L.VARIANT_CSA, "ballot": L.VARIANT_BALLOT}
+VARIANTS = {"csa": L.VARIANT_CSA, "ballot": L.VARIANT_BALLOT, "hybrid": L.VARIANT_HYBRID}
 
 
 def stream_handle(stream=None) -> int:
@@ -67,7 +67,7 @@ def pospopcnt(x: torch.Tensor, k: int, n: int | None = None, byte_offset: int = 
     byte_offset bytes into x's memory (x: any dtype, read as bytes).
 
     Adds into `out` (k int64 counters on x's device; zeros when None) and returns it.
-    Keyword arguments select a launch configuration (variant='csa'|'ballot', depth,
+    Keyword arguments select a launch configuration (variant='csa'|'ballot'|'hybrid', depth,
     block_threads, blocks_per_cu, grid); every configuration gives the same counts."""
     if k not in (8, 16, 32, 64):
         raise ValueError("k must be 8, 16, 32 or 64")

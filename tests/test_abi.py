@@ -79,8 +79,8 @@ def test_k64_arguments(lib):
     assert lib.pospopcnt_u64(0x1000, 2**61, 0x8, None) == 4
     # counts (64 x 8 bytes) ending inside the input
     assert lib.pospopcnt_u64(0x1000, 8, 0x1000 - 64 * 8 + 8, None) == 8
-    # the ballot variant has no 64-bit form; other configuration errors as for k <= 32
-    for cfg in (L.LaunchConfig(variant=1), L.LaunchConfig(depth=12),
+    # the ballot variants have no 64-bit form; other configuration errors as for k <= 32
+    for cfg in (L.LaunchConfig(variant=1), L.LaunchConfig(variant=2), L.LaunchConfig(depth=12),
                 L.LaunchConfig(block_threads=512), L.LaunchConfig(grid=-1)):
         assert lib.pospopcnt_ex(0x1000, 64, 64, 0x80000, None, ctypes.byref(cfg)) == 7
 

@@ -46,7 +46,9 @@ def test_lengths_and_offsets(k):
 @pytest.mark.parametrize("k", KS)
 @pytest.mark.parametrize("cfg", [
     dict(variant="csa", depth=8), dict(variant="csa", depth=16), dict(variant="csa", depth=32),
-    dict(variant="ballot"), dict(block_threads=64), dict(block_threads=128),
+    dict(variant="ballot"), dict(variant="hybrid", depth=8), dict(variant="hybrid", depth=16),
+    dict(variant="hybrid", depth=32, block_threads=64), dict(block_threads=64),
+    dict(block_threads=128),
     dict(grid=1), dict(grid=7), dict(blocks_per_cu=1), dict(depth=32, grid=3, block_threads=64),
 ], ids=lambda c: "-".join(f"{a}{b}" for a, b in c.items()))
 def test_launch_configs_agree(k, cfg):
