@@ -51,8 +51,7 @@ struct Codes {
 
     // The masked path: a tile that may hold ids >= C, or dwords that are not
     // input (unit[i] false: the missing units of a partial tile).  Those ids must
-    // add nothing to the classes.  u16 ids with C = 16, 32 get no code (dead_ids,
-    // make<true>).  Otherwise some get a stand-in code that take_back() later
+    // add nothing to the classes; each gets a stand-in code that take_back() later
     // removes, *ph counting the stand-ins:
     // - C = 8 (make_masked): the byte table of make() applied to the raw ids (u8)
     //   or to their low bytes (u16).  Selectors 8..11 copy the sign of table
@@ -61,19 +60,19 @@ struct Codes {
     //   an id >= 8 (0x00, or 0xFF: one in every class).  A u16 id whose high byte
     //   is not zero is cleared by the mask table below applied to its high byte.
     //   Bits 0 and 1 both set mark exactly the 0xFF bytes; *ph counts them.
-    // - C = 16, 32 (clear_ids, then make<false>): a byte table gives each id a
-    //   mask byte, 0x00 for ids < C and 0xFF otherwise (table {0xFFFFFFFF :
-    //   0xFFFFFF00}, indexed by the id's bits above LOGC: bits 5..7 for C = 32;
-    //   bits 4..7 for C = 16, with bit 3 of the index also set in bit 0 so that
-    //   selector 12, which gives zero, never occurs and 8..11 copy the sign of a
-    //   0xFF byte).
-    //   Masked ids become id 0 in place, whose code lands in class 0; *ph adds
-    //   the mask's popcount, 8 per such id.
-    static constexpr bool CLEARS_IDS = IDB == 1 && C != 8;
+    // - C = 16, 32 (clear_ids, then make): each id gets a mask of all ones when it
+    //   is >= C, and masked ids become id 0 in place, whose code lands in class 0;
+    //   *ph adds the mask's popcount, 8 per such u8 id and 16 per u16 id.  For u8
+    //   ids a byte table gives the mask bytes (table {0xFFFFFFFF : 0xFFFFFF00}:
+    //   0x00 at index 0, 0xFF elsewhere), indexed by the id's bits above LOGC: bits
+    //   5..7 for C = 32; bits 4..7 for C = 16, with bit 3 of the index also set in
+    //   bit 0 so that selector 12, which gives zero, never occurs and 8..11 copy
+    //   the sign of a 0xFF byte.  For u16 ids dead_ids gives the mask halves.
+    static constexpr bool CLEARS_IDS = C != 8;
 
     __device__ static __forceinline__ void make_masked(uint32_t* code, const uint32_t* in,
                                                        const bool* unit, uint32_t* ph) {
-        static_assert(!CLEARS_IDS, "u8 ids with C = 16, 32 go through clear_ids");
+        static_assert(!CLEARS_IDS, "C = 16, 32 go through clear_ids");
         if constexpr (C == 8 && IDB == 1) {
 #pragma unroll
             for (int i = 0; i < NIN; ++i) {
@@ -82,7 +81,7 @@ struct Codes {
                 code[i] = unit[i] ? raw : 0u;
                 *ph += unit[i] ? (uint32_t)__builtin_popcount(ff) : 0u;
             }
-        } else if constexpr (C == 8) {
+        } else {
 #pragma unroll
             for (int i = 0; i < NIN / 2; ++i) {
                 const uint32_t lo = in[2 * i], hi = in[2 * i + 1];
@@ -97,11 +96,6 @@ struct Codes {
                 code[i] = unit[2 * i] ? c : 0u;
                 *ph += unit[2 * i] ? (uint32_t)__builtin_popcount(ff) : 0u;
             }
-        } else {
-            uint32_t dead[NIN];
-#pragma unroll
-            for (int i = 0; i < NIN; ++i) dead[i] = unit[i] ? dead_ids(in[i]) : 0xFFFFFFFFu;
-            make<true>(code, in, dead);
         }
     }
 
@@ -109,15 +103,16 @@ struct Codes {
                                                      uint32_t* ph) {
 #pragma unroll
         for (int i = 0; i < NIN; ++i) {
-            uint32_t sel;
-            if constexpr (C == 32) {
-                sel = (in[i] >> 5) & 0x07070707u;
+            uint32_t m;
+            if constexpr (IDB == 2) {
+                m = dead_ids(in[i]);
+            } else if constexpr (C == 32) {
+                m = __builtin_amdgcn_perm(0xFFFFFFFFu, 0xFFFFFF00u, (in[i] >> 5) & 0x07070707u);
             } else {
                 const uint32_t h = (in[i] >> 4) & 0x0F0F0F0Fu;
-                sel = h | ((h >> 3) & 0x01010101u);
+                m = __builtin_amdgcn_perm(0xFFFFFFFFu, 0xFFFFFF00u, h | ((h >> 3) & 0x01010101u));
             }
-            const uint32_t m =
-                unit[i] ? __builtin_amdgcn_perm(0xFFFFFFFFu, 0xFFFFFF00u, sel) : 0xFFFFFFFFu;
+            m = unit[i] ? m : 0xFFFFFFFFu;
             *ph += (uint32_t)__builtin_popcount(m);
             in[i] &= ~m;
         }
@@ -128,43 +123,27 @@ struct Codes {
         if constexpr (C == 8) {
 #pragma unroll
             for (int i = 0; i < C; ++i) tot[i] -= ph;
-        } else if constexpr (IDB == 1) {
-            tot[0] -= ph / 8;
+        } else {
+            tot[0] -= ph / (8 * IDB);
         }
     }
 
-    // Code dwords of NIN input dwords; dead[i] marks ids of in[i] that get no code.
-    // C = 8: one byte-table lookup per four codes (v_perm_b32: byte b of the result
-    // is byte sel_b of {S0:S1}; the table {0x80402010 : 0x08040201} holds 1 << j at
-    // byte j, and selector 0x0C yields zero, which is what a dead id is mapped to).
-    // C = 16: packed 16-bit shifts, two codes per op, dead halves masked.  C = 32:
-    // one byte- or word-selecting shift per id, dead ids masked.
-    // With MASKED false every id is known to be below C (dead is not read): the same
-    // codes without the masking, which is most of the arithmetic for C = 32.
-    template <bool MASKED>
-    __device__ static __forceinline__ void make(uint32_t* code, const uint32_t* in,
-                                                const uint32_t* dead) {
-        // Dead ids are zeroed first, so that every shift amount below is in range;
-        // the code each of them then gets is cleared again.
-        uint32_t live[NIN], dd[NIN];
-#pragma unroll
-        for (int i = 0; i < NIN; ++i) {
-            dd[i] = MASKED ? dead[i] : 0u;
-            live[i] = in[i] & ~dd[i];
-        }
+    // Code dwords of NIN input dwords whose ids are all below C.  C = 8: one
+    // byte-table lookup per four codes (v_perm_b32: byte b of the result is byte
+    // sel_b of {S0:S1}; the table {0x80402010 : 0x08040201} holds 1 << j at byte
+    // j).  C = 16: packed 16-bit shifts, two codes per op.  C = 32: one byte- or
+    // word-selecting shift per id.
+    __device__ static __forceinline__ void make(uint32_t* code, const uint32_t* in) {
         if constexpr (C == 8) {
             if constexpr (IDB == 1) {
 #pragma unroll
                 for (int i = 0; i < NIN; ++i)
-                    code[i] = __builtin_amdgcn_perm(0x80402010u, 0x08040201u,
-                                                    live[i] | (dd[i] & 0x0C0C0C0Cu));
+                    code[i] = __builtin_amdgcn_perm(0x80402010u, 0x08040201u, in[i]);
             } else {
 #pragma unroll
                 for (int i = 0; i < NIN / 2; ++i) {
-                    const uint32_t lo = live[2 * i] | (dd[2 * i] & 0x000C000Cu);
-                    const uint32_t hi = live[2 * i + 1] | (dd[2 * i + 1] & 0x000C000Cu);
                     // the four id bytes, then the table lookup
-                    const uint32_t sel = __builtin_amdgcn_perm(hi, lo, 0x06040200u);
+                    const uint32_t sel = __builtin_amdgcn_perm(in[2 * i + 1], in[2 * i], 0x06040200u);
                     code[i] = __builtin_amdgcn_perm(0x80402010u, 0x08040201u, sel);
                 }
             }
@@ -175,20 +154,16 @@ struct Codes {
 #pragma unroll
                 for (int i = 0; i < NIN; ++i) {
                     // ids 0 and 1 (2 and 3) widened to the two 16-bit shift amounts
-                    const uint32_t a = __builtin_amdgcn_perm(0u, live[i], 0x0C010C00u);
-                    const uint32_t b = __builtin_amdgcn_perm(0u, live[i], 0x0C030C02u);
-                    const uint32_t da = __builtin_amdgcn_perm(0u, dd[i], 0x01010000u);
-                    const uint32_t db = __builtin_amdgcn_perm(0u, dd[i], 0x03030202u);
-                    code[2 * i] =
-                        __builtin_bit_cast(uint32_t, one << __builtin_bit_cast(u16x2, a)) & ~da;
+                    const uint32_t a = __builtin_amdgcn_perm(0u, in[i], 0x0C010C00u);
+                    const uint32_t b = __builtin_amdgcn_perm(0u, in[i], 0x0C030C02u);
+                    code[2 * i] = __builtin_bit_cast(uint32_t, one << __builtin_bit_cast(u16x2, a));
                     code[2 * i + 1] =
-                        __builtin_bit_cast(uint32_t, one << __builtin_bit_cast(u16x2, b)) & ~db;
+                        __builtin_bit_cast(uint32_t, one << __builtin_bit_cast(u16x2, b));
                 }
             } else {
 #pragma unroll
                 for (int i = 0; i < NIN; ++i)
-                    code[i] = __builtin_bit_cast(uint32_t, one << __builtin_bit_cast(u16x2, live[i])) &
-                              ~dd[i];
+                    code[i] = __builtin_bit_cast(uint32_t, one << __builtin_bit_cast(u16x2, in[i]));
             }
         } else {
 #pragma unroll
@@ -196,9 +171,7 @@ struct Codes {
 #pragma unroll
                 for (int j = 0; j < IDS_PER_IN; ++j) {
                     const int sh = 32 / IDS_PER_IN * j;
-                    const uint32_t keep =
-                        ~(uint32_t)__builtin_amdgcn_sbfe((int)dd[i], sh, 32 / IDS_PER_IN);
-                    code[i * IDS_PER_IN + j] = (1u << ((live[i] >> sh) & IDMASK)) & keep;
+                    code[i * IDS_PER_IN + j] = 1u << ((in[i] >> sh) & IDMASK);
                 }
             }
         }
@@ -234,7 +207,7 @@ __device__ __forceinline__ uint32_t onehot_step(uint32_t (&B)[LOGD], uint32_t& p
     // across the join (a value merged there costs a register copy per id on the
     // fast path).
     if (clean) {
-        K::template make<false>(code, in, nullptr);
+        K::make(code, in);
         return Circuit<LOGD>::run(B, code);
     }
     if constexpr (K::CLEARS_IDS) {
@@ -243,7 +216,7 @@ __device__ __forceinline__ uint32_t onehot_step(uint32_t (&B)[LOGD], uint32_t& p
         // branches' code: the circuit keeps every class's weighted sum whatever
         // the order of its inputs.
         K::clear_ids(in, unit, &ph);
-        K::template make<false>(code, in, nullptr);
+        K::make(code, in);
         uint32_t rev[K::NCODE];
 #pragma unroll
         for (int i = 0; i < K::NCODE; ++i) rev[i] = code[K::NCODE - 1 - i];
