@@ -118,3 +118,30 @@ def test_constant_ids_closed_form(bins):
         exp = np.zeros(bins + 1, np.int64)
         exp[min(v, bins)] = n
         assert (got == exp).all(), ("u16", bins, v, got)
+
+
+@pytest.fixture(scope="module")
+def ids_16gib():
+    buf = torch.empty(1 << 34, dtype=torch.uint8, device="cuda")
+    yield buf
+    del buf
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("id_bytes,bins,p_invalid", [
+    (1, 8, 0.0), (1, 16, 0.0), (1, 32, 0.0), (2, 8, 0.0), (2, 16, 0.0), (2, 32, 0.0),
+    (1, 8, 0.01), (2, 16, 0.01)])
+def test_full_size_benchmark_workload(ids_16gib, id_bytes, bins, p_invalid):
+    """The benchmark's 16 GiB cases in its launch configuration (the defaults): one
+    GiB of Zipf(1.1) ids generated and repeated 16 times, so the exact histogram is
+    16 times the oracle's histogram of that GiB."""
+    gen = 1 << 30
+    host = I.generate(gen, I.Dist.ids(8 * id_bytes, bins, 1.1, p_invalid), SEED + 40 + bins)
+    exp = 16 * expected(host, gen // id_bytes, id_bytes, bins)
+    say(f"histogram 16 GiB id_bytes={id_bytes} bins={bins} p_invalid={p_invalid}")
+    ids_16gib[:gen].copy_(torch.from_numpy(host))
+    for c in range(1, 16):
+        ids_16gib[c * gen:(c + 1) * gen].copy_(ids_16gib[:gen])
+    got = counts_np(api.histogram(ids_16gib, bins, id_bytes=id_bytes))
+    assert (got == exp).all(), (id_bytes, bins, p_invalid)
+    assert got.sum() == (1 << 34) // id_bytes
