@@ -153,3 +153,36 @@ def test_planes_large():
     got = counts_np(api.pospopcnt_planes([b for b, _ in bufs], n=n,
                                          byte_offsets=[o for _, o in bufs]))
     assert (got == exp).all()
+
+
+@pytest.mark.timeout(900)
+def test_full_size_benchmark_workloads():
+    """The benchmark's wide cases at full size in their default launch shapes, against
+    the oracle over all 16 GiB: one stream of 2^31 64-bit words, then the same bytes
+    as 4 planes of 2^31 16-bit limbs (4 GiB each; plane j counted by the plain
+    definition into counters 16j .. 16j+15)."""
+    nbytes = 1 << 34
+    free, _ = torch.cuda.mem_get_info()
+    if free < nbytes + (1 << 30):
+        pytest.skip(f"needs {nbytes >> 30} GiB of free device memory")
+    say("wide 16 GiB: generating")
+    host = np.empty(nbytes, np.uint8)
+    chunk = 1 << 30
+    dev = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    pinned = torch.empty(chunk, dtype=torch.uint8).pin_memory()
+    for first in range(0, nbytes, chunk):
+        I.fill(host[first:first + chunk], I.Dist.uniform(), SEED + 50, first_byte=first)
+        pinned.numpy()[:] = host[first:first + chunk]
+        dev[first:first + chunk].copy_(pinned, non_blocking=False)
+    n = nbytes // 8
+    say("wide 16 GiB: k = 64")
+    got = counts_np(api.pospopcnt_u64(dev, n=n))
+    assert (got == oracle_counts(host, n, 64, threads=I.default_threads())).all()
+    m, per = 4, nbytes // 4
+    say("wide 16 GiB: 4 planes")
+    got = counts_np(api.pospopcnt_planes([dev[j * per:(j + 1) * per] for j in range(m)]))
+    exp = np.concatenate([oracle_counts(host[j * per:(j + 1) * per], per // 2, 16,
+                                        threads=I.default_threads()) for j in range(m)])
+    assert (got == exp).all()
+    del dev
+    torch.cuda.empty_cache()
