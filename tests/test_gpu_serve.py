@@ -130,3 +130,29 @@ def test_large_and_small_batches_share_slots(workload, in_place):
     for j, i in enumerate(pick):
         k = int(trace.ks[i])
         assert (comps["counts"][j][:k].astype(np.int64) == expected(trace, pools, i)).all(), j
+
+
+@pytest.mark.parametrize("in_place", [False, True], ids=["copy", "in_place"])
+def test_benchmark_configuration_sampled(in_place):
+    """One second of the benchmark's C5 trace in its configuration (512 MiB pools, a
+    64 GiB arena, 4096 requests in flight, batches of up to 1024, 4 streams): every
+    request succeeds, and 150 of them (the 30 largest among them) equal the oracle."""
+    seed = I.BASE_SEED + 4
+    pool = 1 << 29
+    trace = I.serving_trace(50_000, 1.0, seed, pool_bytes=pool)
+    pools = S.Pools(trace, pool, seed)
+    reqs = pools.requests(trace)
+    say(f"serve C5 config: {len(reqs)} requests, {trace.nbytes.sum() / 1e9:.1f} GB, "
+        f"in_place={in_place}")
+    srv = S.Server(64 << 30, max_requests=4096, max_batch=1024, streams=4, in_place=in_place)
+    comps = srv.run_trace(reqs)
+    srv.close()
+    assert (comps["status"] == 0).all()
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    sample = np.unique(np.concatenate([rng.choice(len(reqs), 120, replace=False),
+                                       np.argsort(trace.nbytes)[-30:]]))
+    for i in sample:
+        k = int(trace.ks[i])
+        assert (comps["counts"][i][:k].astype(np.int64) == expected(trace, pools, i)).all(), i
+    del pools
+    torch.cuda.empty_cache()
