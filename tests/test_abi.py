@@ -1,6 +1,7 @@
 """C-ABI contract checks that need no GPU: the library loads, exports every
 function include/*.h declares, and rejects bad arguments before any HIP call."""
 import ctypes
+import importlib.util
 import os
 import re
 import subprocess
@@ -219,3 +220,26 @@ def test_histogram_arguments(lib):
     assert lib.ppc_histogram_ex(0x1000, 5, 3, 8, 0x8000, None, None) == 7
     bad = L.LaunchConfig(depth=16)
     assert lib.ppc_histogram_ex(0x1000, 5, 1, 8, 0x8000, None, ctypes.byref(bad)) == 7
+
+
+def _c_caller():
+    exe = os.path.join(ROOT, "tests", "c_abi", "abi_check")
+    if not os.path.exists(exe):
+        spec = importlib.util.spec_from_file_location(
+            "ppc_c_abi_build", os.path.join(ROOT, "tests", "c_abi", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()
+    return exe
+
+
+def test_header_is_strict_c99_and_callable_from_c():
+    """include/pospopcnt.h compiles as strict C99, and a C program linked against the
+    library gets the documented statuses for calls that launch nothing."""
+    spec = importlib.util.spec_from_file_location(
+        "ppc_c_abi_build", os.path.join(ROOT, "tests", "c_abi", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    mod.check_header_c99()
+    res = subprocess.run([_c_caller(), "cpu"], capture_output=True, text=True, timeout=60)
+    assert res.returncode == 0, res.stdout + res.stderr
