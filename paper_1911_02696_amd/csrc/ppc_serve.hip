@@ -313,9 +313,24 @@ class HipExecutor : public Executor {
         const bool direct =
             in_place_ && n <= kSmallBatch &&
             (uint64_t)small_batch_grid(plans_[s.stream], n, bytes) * n <= kDirectReads;
+        // A failure once work is queued: wait for that work, so that no kernel still
+        // writes into the slabs the scheduler frees when it fails these requests, and
+        // clear the counters it may have added to, which the slot's next launch
+        // expects at zero.
+        auto abandon = [&](int status) {
+            (void)hipStreamSynchronize(st);
+            (void)hipMemsetAsync(s.d_counts, 0, 256ull * n, st);
+            (void)hipStreamSynchronize(st);
+            return status;
+        };
+#define PPC_HIP_QUEUED(call)                                       \
+    do {                                                           \
+        const hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return abandon(::ppc::fail_hip(e_)); \
+    } while (0)
         if (!direct) {
             const size_t meta = in_place_ ? sizeof(ppc_desc) * n : seg_off + sizeof(CopySeg) * n;
-            PPC_HIP(hipMemcpyAsync(s.d_meta, s.h_meta, meta, hipMemcpyHostToDevice, st));
+            PPC_HIP_QUEUED(hipMemcpyAsync(s.d_meta, s.h_meta, meta, hipMemcpyHostToDevice, st));
         }
         if (units) {
             const CopySeg* d_segs = (const CopySeg*)(s.d_meta + seg_off);
@@ -323,17 +338,20 @@ class HipExecutor : public Executor {
             const uint64_t want = (units + 1023) / 1024;
             const uint32_t grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)cus_ * 8);
             void* args[] = {(void*)&d_segs, (void*)&n, &units};
-            PPC_HIP(hipLaunchKernel((const void*)copy_segments, dim3(grid), dim3(256), args, 0, st));
+            PPC_HIP_QUEUED(
+                hipLaunchKernel((const void*)copy_segments, dim3(grid), dim3(256), args, 0, st));
         }
         // the slot's counters are zero here (cleared after the slot's previous use)
         const int bst =
             batch_zeroed(plans_[s.stream], direct ? s.h_descs() : s.d_descs(), n, st, bytes);
-        if (bst) return bst;
-        PPC_HIP(hipMemcpyAsync(s.h_counts, s.d_counts, 256ull * n, hipMemcpyDeviceToHost, st));
-        PPC_HIP(hipEventRecord(s.done, st));
+        if (bst) return abandon(bst);
+        PPC_HIP_QUEUED(
+            hipMemcpyAsync(s.h_counts, s.d_counts, 256ull * n, hipMemcpyDeviceToHost, st));
+        PPC_HIP_QUEUED(hipEventRecord(s.done, st));
         // Clear the counters used, for the slot's next launch on this same stream;
         // enqueued after the event, so the results do not wait for it.
-        PPC_HIP(hipMemsetAsync(s.d_counts, 0, 256ull * n, st));
+        PPC_HIP_QUEUED(hipMemsetAsync(s.d_counts, 0, 256ull * n, st));
+#undef PPC_HIP_QUEUED
         s.busy = true;
         s.n = n;
         *handle = si;
