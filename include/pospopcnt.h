@@ -216,8 +216,9 @@ typedef struct ppc_plan ppc_plan;
  * > 2^26), PPC_ERR_HIP. */
 int ppc_plan_create(const ppc_workload_hint* hint, ppc_plan** plan);
 
-/* Releases the plan's scratch and graphs.  Work enqueued with the plan must have
- * completed.  NULL is accepted. */
+/* Releases the plan's scratch and graphs, after waiting for the plan's device to
+ * finish its work (so that work enqueued with the plan completes first; the call
+ * synchronises that device).  NULL is accepted. */
 int ppc_plan_destroy(ppc_plan* plan);
 
 /* Counts every stream of the m descriptors at d_descs (device memory) with a

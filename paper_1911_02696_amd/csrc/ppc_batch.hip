@@ -705,6 +705,9 @@ int ppc_plan_destroy(ppc_plan* pl) {
     int dev = -1;
     (void)hipGetDevice(&dev);
     if (dev != pl->device) (void)hipSetDevice(pl->device);
+    // Work enqueued with the plan reads its scratch (and may replay its graph): wait
+    // for the device, so that dropping a plan early frees nothing still in use.
+    (void)hipDeviceSynchronize();
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
     if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
     if (pl->scratch) (void)hipFree(pl->scratch);
