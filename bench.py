@@ -165,8 +165,15 @@ def batched_leg(args, torch, api):
                               counts.data_ptr() + 256 * np.arange(m))
     descs = B.to_device(desc_host)
     stream = torch.cuda.current_stream()
-    plan = B.Plan(m, graph=True)
-    tuned_ms = plan.autotune(descs)
+    profile = args.batched_profile
+    plan = B.Plan(m, graph=not profile)
+    if profile:
+        # for counter profiling: the tuner's usual choice, set directly, and no graph
+        plan.config = {"depth": 16, "block_threads": 64, "blocks_per_cu": 4,
+                       "stream_weight": 2048}
+        tuned_ms = float("nan")
+    else:
+        tuned_ms = plan.autotune(descs)
 
     def timed(fn, steps):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -186,6 +193,14 @@ def batched_leg(args, torch, api):
     wall, ev = timed(lambda: plan.run(descs), args.steps)
     got = counts.cpu().numpy() // args.steps
     ok_rep = bool((counts.cpu().numpy() == got * args.steps).all())
+
+    if profile:
+        cfg = plan.config
+        del dev
+        plan.close()
+        return {"bytes": total, "streams": m, "value": round(total / wall / 1e9, 2),
+                "unit": "GB/s", "event_ms_per_step": round(ev * 1e3, 4), "config": cfg,
+                "graph": False, "check": {"steps_consistent": ok_rep}}, ok_rep
 
     counts.zero_()
     each_steps = 3
@@ -421,6 +436,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 20,000-stream batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--batched-profile", action="store_true",
+                    help="batched leg for counter profiling: the tuned shape set directly, no "
+                         "graph, no autotuning and no per-stream comparison")
     ap.add_argument("--legs", default="single,batched,serving,onehot,wide",
                     help="comma-separated subset of single,batched,serving,onehot,wide to run "
                          "(the full JSON line is printed only when the single leg runs)")
