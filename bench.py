@@ -247,14 +247,14 @@ def serving_leg(args, torch, api):
     from paper_1911_02696_amd import serve as S
     seed = SEED + 4
     pool_bytes = 1 << 29
-    trace = I.serving_trace(50_000, args.serve_seconds, seed, pool_bytes=pool_bytes)
+    trace = I.serving_trace(args.serve_rate, args.serve_seconds, seed, pool_bytes=pool_bytes)
     print(f"[bench] serving: {len(trace.arrival)} requests over {args.serve_seconds} s, "
           f"{trace.nbytes.sum() / 1e12:.2f} TB", file=sys.stderr, flush=True)
     pools = S.Pools(trace, pool_bytes, seed)
     reqs = pools.requests(trace)
-    report = {"workload": "Poisson arrivals 50,000 req/s, lengths log-uniform in [2^10, 2^26] "
-                          "words, k uniform in {8,16,32}, one-hot Zipf(1.1) or Bernoulli(0.5) "
-                          "inputs from device-resident pools", "arena_bytes": 64 << 30,
+    report = {"workload": f"Poisson arrivals {args.serve_rate:,.0f} req/s, lengths log-uniform in "
+                          "[2^10, 2^26] words, k uniform in {8,16,32}, one-hot Zipf(1.1) or "
+                          "Bernoulli(0.5) inputs from device-resident pools", "arena_bytes": 64 << 30,
               "max_requests": 4096, "max_batch": 1024, "streams": 4}
     ok = True
     for mode, seconds in (("copy", args.serve_seconds), ("in_place", min(3.0, args.serve_seconds))):
@@ -443,6 +443,8 @@ def main():
                     help="comma-separated subset of single,batched,serving,onehot,wide to run "
                          "(the full JSON line is printed only when the single leg runs)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=50_000.0,
+                    help="Poisson arrival rate of the serving leg, requests/s")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-reference", type=int, default=0, metavar="BYTES",
                     help="only run --steps device-to-device copies of BYTES bytes (a plain copy "
@@ -644,6 +646,9 @@ def main():
                      "algorithmic_bytes_per_launch": nbytes,
                      "avg_launch_ms": round(avg_kernel * 1e3, 4),
                      "min_launch_ms": round(float(per.min()) * 1e3, 4),
+                     "median_launch_ms": round(float(np.median(per)) * 1e3, 4),
+                     "p10_launch_ms": round(float(np.percentile(per, 10)) * 1e3, 4),
+                     "p90_launch_ms": round(float(np.percentile(per, 90)) * 1e3, 4),
                      "kernel_source_sha256": src_hash},
         "ceiling": ceiling,
         "data_independence": data_independence,
