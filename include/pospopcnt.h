@@ -150,7 +150,8 @@ int ppc_read_ceiling(const void* ptr, uint64_t nbytes, uint64_t* sink, ppc_strea
  * their one-hot codes in registers, so the encoded stream is never written.
  *   ids    device pointer to n unsigned ids of 1 (u8) or 2 (u16) bytes,
  *          little-endian; u16 ids must be 2-byte aligned (PPC_ERR_ALIGN).
- *   bins   8, 16 or 32 (PPC_ERR_WIDTH otherwise).
+ *   bins   1 .. 32 (PPC_ERR_WIDTH otherwise); the codes are 8, 16 or 32 bits, the
+ *          narrowest that holds bins categories.
  *   counts device, 8-byte aligned, bins + 1 uint64 entries, added into:
  *          counts[c] += number of ids equal to c (c < bins) and
  *          counts[bins] += number of ids >= bins (ids without a code).

@@ -163,8 +163,8 @@ def histogram(ids: torch.Tensor, bins: int, id_bytes: int | None = None, n: int 
     one-hot codes.  Adds into `out` (bins + 1 int64 counters: one per category and a
     last one for ids >= bins) and returns it.  id_bytes defaults to the tensor's
     element size (1 or 2)."""
-    if bins not in (8, 16, 32):
-        raise ValueError("bins must be 8, 16 or 32")
+    if not 1 <= bins <= 32:
+        raise ValueError("bins must be 1 .. 32")
     id_bytes = id_bytes or ids.element_size()
     if id_bytes not in (1, 2):
         raise ValueError("ids are 1 or 2 bytes")

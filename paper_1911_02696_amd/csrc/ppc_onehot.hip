@@ -244,9 +244,11 @@ __device__ __forceinline__ uint32_t edge_onehot(const Edges& e, int lane, uint32
     return id < (uint32_t)C ? 1u << id : 0u;
 }
 
+// bins <= C categories counted with C-bit codes: classes bins .. C-1 hold ids that
+// have a code but no category, and are flushed into counts[bins] with the rest.
 template <int C, int IDB>
 __global__ void __launch_bounds__(kOnehotThreads)
-onehot_kernel(const u32x4* __restrict__ body, uint64_t units, Edges edges,
+onehot_kernel(const u32x4* __restrict__ body, uint64_t units, Edges edges, uint32_t bins,
               unsigned long long* __restrict__ counts) {
     constexpr int U = 4;
     constexpr int LOGD = C == 8 ? (IDB == 1 ? 4 : 3) : C == 16 ? (IDB == 1 ? 5 : 4)
@@ -301,22 +303,29 @@ onehot_kernel(const u32x4* __restrict__ body, uint64_t units, Edges edges,
     if (lane % G == 0) red[wave][lane / G] = v;
     if (lane == 0) red_other[wave] = other;
     __syncthreads();
-    block_flush<C>(red, wpb, C, 0u, counts);
-    if (threadIdx.x == C) {
+    const uint32_t p = threadIdx.x;
+    if (p < bins) {
         unsigned long long s = 0;
-        for (int w = 0; w < wpb; ++w) s += red_other[w];
-        if (s) atomicAdd(counts + C, s);
+        for (int w = 0; w < wpb; ++w) s += red[w][p];
+        if (s) atomicAdd(counts + p, s);
+    } else if (p == bins) {
+        unsigned long long s = 0;
+        for (int w = 0; w < wpb; ++w) {
+            s += red_other[w];
+            for (int cls = (int)bins; cls < C; ++cls) s += red[w][cls];
+        }
+        if (s) atomicAdd(counts + bins, s);
     }
 }
 
-using OnehotKernel = void (*)(const u32x4*, uint64_t, Edges, unsigned long long*);
+using OnehotKernel = void (*)(const u32x4*, uint64_t, Edges, uint32_t, unsigned long long*);
 
-static const void* onehot_of(int bins, int id_bytes) {
+static const void* onehot_of(int code_bits, int id_bytes) {
     static OnehotKernel table[2][3] = {
         {onehot_kernel<8, 1>, onehot_kernel<16, 1>, onehot_kernel<32, 1>},
         {onehot_kernel<8, 2>, onehot_kernel<16, 2>, onehot_kernel<32, 2>},
     };
-    return (const void*)table[id_bytes - 1][bins == 8 ? 0 : bins == 16 ? 1 : 2];
+    return (const void*)table[id_bytes - 1][code_bits == 8 ? 0 : code_bits == 16 ? 1 : 2];
 }
 
 // Default launch shape per (categories, id width), from a sweep of block sizes 64..256
@@ -328,14 +337,16 @@ struct OnehotShape {
     int threads, blocks_per_cu;
 };
 
-static OnehotShape onehot_shape(int bins) {
-    return bins == 8 ? OnehotShape{64, 3} : OnehotShape{256, 1};
+static OnehotShape onehot_shape(int code_bits) {
+    return code_bits == 8 ? OnehotShape{64, 3} : OnehotShape{256, 1};
 }
 
 static int launch_histogram(const void* ids, uint64_t n, int id_bytes, int bins,
                             uint64_t* counts, ppc_stream stream, const ppc_launch_config* cfg) {
     if (id_bytes != 1 && id_bytes != 2) return PPC_ERR_ARG;
-    if (bins != 8 && bins != 16 && bins != 32) return PPC_ERR_WIDTH;
+    if (bins < 1 || bins > 32) return PPC_ERR_WIDTH;
+    // codes of 8, 16 or 32 bits: the narrowest that holds every category
+    const int code_bits = bins <= 8 ? 8 : bins <= 16 ? 16 : 32;
     if (n == 0) return PPC_OK;
     if (n > UINT64_MAX / (uint64_t)id_bytes) return PPC_ERR_RANGE;
     const uint64_t nbytes = n * (uint64_t)id_bytes;
@@ -349,7 +360,7 @@ static int launch_histogram(const void* ids, uint64_t n, int id_bytes, int bins,
     ppc_launch_config c = {};
     if (cfg) c = *cfg;
     if (c.variant != PPC_VARIANT_CSA || (c.depth != 0)) return PPC_ERR_ARG;
-    const OnehotShape dflt = onehot_shape(bins);
+    const OnehotShape dflt = onehot_shape(code_bits);
     const int threads = c.block_threads ? c.block_threads : dflt.threads;
     if (threads < kWave || threads > kOnehotThreads || threads % kWave) return PPC_ERR_ARG;
     if (c.blocks_per_cu < 0 || c.grid < 0) return PPC_ERR_ARG;
@@ -376,8 +387,9 @@ static int launch_histogram(const void* ids, uint64_t n, int id_bytes, int bins,
     const u32x4* body = (const u32x4*)s.body;
     uint64_t units = s.units;
     unsigned long long* cp = (unsigned long long*)counts;
-    void* args[] = {&body, &units, &e, &cp};
-    PPC_HIP(hipLaunchKernel(onehot_of(bins, id_bytes), dim3((uint32_t)grid), dim3(threads), args,
+    uint32_t nbins = (uint32_t)bins;
+    void* args[] = {&body, &units, &e, &nbins, &cp};
+    PPC_HIP(hipLaunchKernel(onehot_of(code_bits, id_bytes), dim3((uint32_t)grid), dim3(threads), args,
                             0, (hipStream_t)stream));
     return PPC_OK;
 }

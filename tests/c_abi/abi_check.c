@@ -46,7 +46,8 @@ static int cpu_checks(void) {
     EXPECT(pospopcnt_u64((const void*)0x1000, (uint64_t)1 << 61, fake_counts, NULL) ==
            PPC_ERR_RANGE);
     EXPECT(ppc_histogram_u8(NULL, 10, 8, fake_counts, NULL) == PPC_ERR_NULL);
-    EXPECT(ppc_histogram_u8((const void*)0x1000, 10, 12, fake_counts, NULL) == PPC_ERR_WIDTH);
+    EXPECT(ppc_histogram_u8((const void*)0x1000, 10, 33, fake_counts, NULL) == PPC_ERR_WIDTH);
+    EXPECT(ppc_histogram_u8((const void*)0x1000, 10, 0, fake_counts, NULL) == PPC_ERR_WIDTH);
     for (int st = 0; st <= 9; ++st) {
         const char* s = ppc_status_string(st);
         EXPECT(s != NULL && strlen(s) > 0);

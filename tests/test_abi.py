@@ -209,7 +209,7 @@ def test_plan_needs_a_device(lib):
 
 def test_histogram_arguments(lib):
     assert lib.ppc_histogram_u8(None, 0, 8, None, None) == 0           # n = 0: no-op
-    for bins in (0, 4, 12, 64):
+    for bins in (0, 33, 64):
         assert lib.ppc_histogram_u8(0x1000, 5, bins, 0x8000, None) == 3
     assert lib.ppc_histogram_u8(None, 5, 8, 0x8000, None) == 1
     assert lib.ppc_histogram_u8(0x1000, 5, 8, None, None) == 1

@@ -145,3 +145,35 @@ def test_full_size_benchmark_workload(ids_16gib, id_bytes, bins, p_invalid):
     got = counts_np(api.histogram(ids_16gib, bins, id_bytes=id_bytes))
     assert (got == exp).all(), (id_bytes, bins, p_invalid)
     assert got.sum() == (1 << 34) // id_bytes
+
+
+@pytest.mark.parametrize("id_bytes", [1, 2])
+@pytest.mark.parametrize("bins", [1, 3, 7, 9, 13, 17, 24, 31])
+def test_histogram_any_bin_count(id_bytes, bins):
+    """Category counts that are not a code width: the ids in [bins, code bits) have a
+    code but no category and must be counted as outside (the generator draws ids
+    outside the categories as bins .. bins + 6, exactly that range)."""
+    lengths = [1, 15, 16, 17, 4097, 100_003]
+    host = I.generate(max(lengths) * id_bytes, I.Dist.ids(8 * id_bytes, bins, 1.1, 0.1),
+                      SEED + 60 + bins)
+    for off in (0, 2, 5) if id_bytes == 1 else (0, 2, 6):
+        say(f"histogram any bins id_bytes={id_bytes} bins={bins} offset={off}")
+        buf, o = to_device(host, off)
+        for n in lengths:
+            got = counts_np(api.histogram(buf, bins, id_bytes=id_bytes, n=n, byte_offset=o))
+            assert (got == expected(host, n, id_bytes, bins)).all(), (id_bytes, bins, off, n)
+
+
+@pytest.mark.parametrize("bins", [1, 5, 12, 20])
+def test_constant_ids_any_bin_count(bins):
+    """Closed form for bin counts that are not a code width: a constant stream of id v
+    falls in class v when v < bins and outside otherwise, also for v between bins and
+    the code width."""
+    n = 70_001
+    buf = torch.empty(n + 16, dtype=torch.uint8, device="cuda")
+    for v in list(range(40)) + [127, 255]:
+        buf.fill_(v)
+        got = counts_np(api.histogram(buf, bins, n=n, byte_offset=3))
+        exp = np.zeros(bins + 1, np.int64)
+        exp[min(v, bins)] = n
+        assert (got == exp).all(), (bins, v, got)
