@@ -5,12 +5,14 @@
 // c is bit c of a bins-bit one-hot word, and the positional population count of
 // the encoded stream is the frequency histogram.  Here each lane loads raw ids
 // (u8 or u16) with the same nontemporal dwordx4 tiles as the counting kernel,
-// turns them into packed one-hot codes in registers (see Codes: four 8-bit, two
-// 16-bit or one 32-bit code per dword; ids >= bins have no code), and feeds the
-// code dwords of a tile to one Harley-Seal circuit of Sec. 2, whose carry enters
-// the cross-tile levels of ppc_tree.h before it is counted per category class as
-// in the counting kernel.  Every id with a code adds one to exactly one class, so
-// the ids >= bins are the ids a lane saw less the sum of its class totals.
+// turns them into packed one-hot codes of C = 8, 16 or 32 bits in registers (the
+// narrowest width that holds bins; see Codes: four 8-bit, two 16-bit or one 32-bit
+// code per dword; ids >= C have no code), and feeds the code dwords of a tile to
+// one Harley-Seal circuit of Sec. 2, whose carry enters the cross-tile levels of
+// ppc_tree.h before it is counted per category class as in the counting kernel.
+// Every id with a code adds one to exactly one class, so the ids >= C are the ids
+// a lane saw less the sum of its class totals; the classes bins .. C-1 join them
+// at the flush.
 // Head and tail ids outside the 16-byte aligned body are expanded one per lane by
 // the first wave; padding never becomes an id.
 #include "ppc_device.h"
