@@ -382,7 +382,10 @@ int ppc_server_get_stats(const ppc_server* server, ppc_server_stats* stats);
  * the server is progressed continuously until all n have completed.  out[i]
  * receives request i's completion (out holds n entries); arrival times in out are
  * on the server clock.  Returns PPC_OK when every request has completed, whatever
- * their individual statuses. */
+ * their individual statuses.  The server must be idle at the call: no request
+ * queued or in flight and no completion left to take (else PPC_ERR_STATE, and
+ * nothing is submitted).  PPC_ERR_STATE also when nothing has progressed for
+ * 120 s (a launch that never finished); the requests still held stay in the server. */
 int ppc_server_run_trace(ppc_server* server, const ppc_request* requests, uint32_t n,
                          ppc_completion* out);
 

@@ -637,7 +637,10 @@ int ppc_server_run_trace(ppc_server* s, const ppc_request* reqs, uint32_t n, ppc
     for (uint32_t i = 1; i < n; ++i)
         if (reqs[i].arrival < reqs[i - 1].arrival) return PPC_ERR_ARG;
     // Requests are submitted with their index as tag; completions are put back in
-    // place with the caller's tag.
+    // place with the caller's tag.  Completions of requests submitted before would
+    // carry other tags, so the server must hold none.
+    if (!s->queue.empty() || !s->admitted.empty() || !s->inflight.empty() || !s->done.empty())
+        return PPC_ERR_STATE;
     const double start = s->now();
     uint32_t next = 0, finished = 0;
     double last_change = start;

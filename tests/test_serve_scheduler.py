@@ -11,6 +11,7 @@ import pytest
 import oracle
 from paper_1911_02696_amd import inputs as I
 from paper_1911_02696_amd import serve as S
+from paper_1911_02696_amd._lib import PpcError
 
 GRANULE = 256
 
@@ -267,6 +268,41 @@ def test_run_trace_respects_arrivals():
     assert (comps["arrival"] - t0 >= w.reqs["arrival"] - 1e-3).all()
     lat = S.latency_summary(comps)
     assert lat["ok"] == 150 and lat["p99_ms"] >= lat["p50_ms"] > 0
+
+
+def test_run_trace_needs_an_idle_server():
+    """A replay indexes its output by request position, so it refuses a server that
+    still holds requests submitted directly (their tags are the caller's own)."""
+    w = Workload(20, 9)
+    ex = FakeExecutor(1 << 20, delay=3)
+    srv = S.Server(1 << 20, max_requests=8, max_batch=4, streams=1, executor=ex.ops)
+    early = w.reqs[:4].copy()
+    early["tag"] = [10 ** 9, 10 ** 9 + 1, 10 ** 9 + 2, 10 ** 9 + 3]
+    srv.submit(early)
+    srv.progress()
+    for held in ("queued or in flight", "completions not taken"):
+        with pytest.raises(PpcError) as err:
+            srv.run_trace(w.reqs[4:])
+        assert err.value.status == 9  # PPC_ERR_STATE
+        assert srv.stats()["submitted"] == 4, held
+        for _ in range(100):
+            srv.progress()
+            if srv.stats()["completed"] == 4:
+                break
+        assert srv.stats()["completed"] == 4
+    comps = srv.take_completions()
+    assert sorted(comps["tag"].tolist()) == early["tag"].tolist()
+    comps = srv.run_trace(w.reqs[4:])
+    assert (comps["tag"] == np.arange(4, 20)).all()
+    check_counts_subset(w, comps)
+
+
+def check_counts_subset(w, comps):
+    for c in comps:
+        t = int(c["tag"])
+        assert c["status"] == 0, (t, c["status"])
+        k = int(w.k[t])
+        assert (c["counts"][:k] == w.expected(t)).all(), f"request {t}"
 
 
 def test_server_argument_checks():
