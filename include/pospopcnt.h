@@ -211,8 +211,9 @@ typedef struct ppc_plan ppc_plan;
 
 /* Creates a plan on the current device.  The plan owns device scratch for
  * max_streams descriptors (a prefix array of 8 bytes per stream, 12 bytes per
- * 2048 streams for the split preparation, a per-block start table and a 1 MiB
- * autotuning sink) and a default configuration.  This is the only batched call
+ * 2048 streams for the split preparation, a per-block start table and an
+ * autotuning sink of 256 bytes per block of the largest grid, 1 MiB on 256
+ * compute units) and a default configuration.  This is the only batched call
  * that allocates.  Errors: PPC_ERR_NULL, PPC_ERR_ARG (max_streams = 0 or
  * > 2^26), PPC_ERR_HIP. */
 int ppc_plan_create(const ppc_workload_hint* hint, ppc_plan** plan);
@@ -247,8 +248,8 @@ int ppc_plan_get_config(const ppc_plan* plan, ppc_batch_config* config);
 /* Errors: PPC_ERR_ARG for a field out of range. */
 int ppc_plan_set_config(ppc_plan* plan, const ppc_batch_config* config);
 
-/* Writes the plan's configuration as a small JSON object (with the device name
- * and architecture) to path / reads it back.  ppc_plan_load returns
+/* Writes the plan's configuration as a small JSON object (with the device
+ * architecture, e.g. "gfx950") to path / reads it back.  ppc_plan_load returns
  * PPC_ERR_STATE if the file was written for another device architecture and
  * PPC_ERR_ARG if it cannot be parsed; the plan is then unchanged. */
 int ppc_plan_save(const ppc_plan* plan, const char* path);
