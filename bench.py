@@ -642,7 +642,9 @@ def main():
         "frac_of_hbm_peak": round(value / HBM_PEAK_GBPS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic, "kernel": kname,
+                     "traffic": traffic["hbm_bytes"] if traffic else None,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled)",
+                     "traffic_detail": traffic, "kernel": kname,
                      "algorithmic_bytes_per_launch": nbytes,
                      "avg_launch_ms": round(avg_kernel * 1e3, 4),
                      "min_launch_ms": round(float(per.min()) * 1e3, 4),
