@@ -3,6 +3,11 @@
 torch supplies device memory and the stream; every step of the count runs in
 the library's HIP kernels.  Counts are returned in int64 storage, which holds
 the same bits as the library's uint64 counters for any total below 2^63.
+
+`stream` is torch's current stream when None, else a torch.cuda.Stream or a raw
+hipStream_t handle.  The caller orders the producers of the inputs (and of a
+supplied `out`) before that stream, as for any asynchronous launch; an output
+the binding allocates itself is ordered by the binding.
 """
 from __future__ import annotations
 
@@ -23,6 +28,26 @@ def stream_handle(stream=None) -> int:
     if isinstance(stream, torch.cuda.Stream):
         return stream.cuda_stream
     return int(stream)
+
+
+def _launch_on(stream, fresh) -> int:
+    """The stream handle to launch on, on the current device.  `fresh` is a tensor
+    this binding has just filled on torch's current stream (None if the caller
+    supplied the output): a launch on another stream first waits for that fill,
+    and the tensor is marked as used by that stream, so that its memory is not
+    handed out again before the launch ends."""
+    cur = torch.cuda.current_stream()
+    if stream is None:
+        return cur.cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        if fresh is not None and stream != cur:
+            stream.wait_stream(cur)
+            fresh.record_stream(stream)
+        return stream.cuda_stream
+    handle = int(stream)
+    if fresh is not None and handle != cur.cuda_stream:
+        cur.synchronize()  # a raw handle: finish the fill before launching there
+    return handle
 
 
 def launch_config(variant="csa", depth=0, block_threads=0, blocks_per_cu=0, grid=0):
@@ -76,10 +101,12 @@ def pospopcnt(x: torch.Tensor, k: int, n: int | None = None, byte_offset: int = 
         n = avail // (k // 8)
     if n < 0 or n * (k // 8) > avail:
         raise ValueError(f"{n} words of {k} bits do not fit in {avail} bytes")
+    fresh = out is None
     out = _counts_tensor(out, k, x.device)
     cfg = launch_config(**config) if config else None
     with torch.cuda.device(x.device):
-        pospopcnt_ptr(x.data_ptr() + byte_offset, n, k, out.data_ptr(), stream, cfg)
+        s = _launch_on(stream, out if fresh else None)
+        pospopcnt_ptr(x.data_ptr() + byte_offset, n, k, out.data_ptr(), s, cfg)
     return out
 
 
@@ -126,11 +153,13 @@ def pospopcnt_planes(planes, n: int | None = None, byte_offsets=None,
     dev = planes[0].device
     if any(p.device != dev for p in planes):
         raise ValueError("planes must be on one device")
+    fresh = out is None
     out = _counts_tensor(out, 16 * m, dev)
     ptrs = (ctypes.c_void_p * m)(*[p.data_ptr() + o for p, o in zip(planes, offs)])
     cfg = launch_config(**config) if config else None
     with torch.cuda.device(dev):
-        check(L.lib().pospopcnt_planes16_ex(ptrs, m, n, out.data_ptr(), stream_handle(stream),
+        s = _launch_on(stream, out if fresh else None)
+        check(L.lib().pospopcnt_planes16_ex(ptrs, m, n, out.data_ptr(), s,
                                             ctypes.byref(cfg) if cfg is not None else None),
               f"pospopcnt_planes16(m={m}, n={n})")
     return out
@@ -144,12 +173,13 @@ def read_ceiling(x: torch.Tensor, nbytes: int | None = None, byte_offset: int = 
     nbytes = avail if nbytes is None else nbytes
     if nbytes > avail:
         raise ValueError("range outside the tensor")
-    if sink is None:
+    fresh = sink is None
+    if fresh:
         sink = torch.zeros(1, dtype=torch.int64, device=x.device)
     cfg = launch_config(**config) if config else None
     with torch.cuda.device(x.device):
-        check(L.lib().ppc_read_ceiling(x.data_ptr() + byte_offset, nbytes, sink.data_ptr(),
-                                       stream_handle(stream),
+        s = _launch_on(stream, sink if fresh else None)
+        check(L.lib().ppc_read_ceiling(x.data_ptr() + byte_offset, nbytes, sink.data_ptr(), s,
                                        ctypes.byref(cfg) if cfg is not None else None),
               "ppc_read_ceiling")
     return sink
@@ -173,11 +203,13 @@ def histogram(ids: torch.Tensor, bins: int, id_bytes: int | None = None, n: int 
         n = avail // id_bytes
     if n < 0 or n * id_bytes > avail:
         raise ValueError(f"{n} ids of {id_bytes} bytes do not fit in {avail} bytes")
+    fresh = out is None
     out = _counts_tensor(out, bins + 1, ids.device)
     cfg = launch_config(**config) if config else None
     with torch.cuda.device(ids.device):
+        s = _launch_on(stream, out if fresh else None)
         check(L.lib().ppc_histogram_ex(ids.data_ptr() + byte_offset, n, id_bytes, bins,
-                                       out.data_ptr(), stream_handle(stream),
+                                       out.data_ptr(), s,
                                        ctypes.byref(cfg) if cfg is not None else None),
               f"ppc_histogram(bins={bins}, n={n})")
     return out

@@ -75,13 +75,22 @@ class Plan:
             raise ValueError(f"{m} descriptors requested, the tensor holds {cap}")
         return descs.data_ptr(), m
 
+    @staticmethod
+    def _keep(descs: torch.Tensor, stream):
+        # The kernels read the descriptors when they run: on a stream other than
+        # the one their memory belongs to, keep that memory from being reused first.
+        if isinstance(stream, torch.cuda.Stream) and stream != torch.cuda.current_stream():
+            descs.record_stream(stream)
+
     def run(self, descs: torch.Tensor, m: int | None = None, stream=None) -> None:
         ptr, m = self._descs(descs, m)
+        self._keep(descs, stream)
         check(L.lib().pospopcnt_batch(self.handle, ptr, m, stream_handle(stream)),
               "pospopcnt_batch")
 
     def autotune(self, descs: torch.Tensor, m: int | None = None, stream=None) -> float:
         ptr, m = self._descs(descs, m)
+        self._keep(descs, stream)
         best = ctypes.c_float(0.0)
         check(L.lib().ppc_plan_autotune(self.handle, ptr, m, stream_handle(stream),
                                         ctypes.byref(best)), "ppc_plan_autotune")

@@ -122,6 +122,28 @@ def test_run_to_run_identical_and_concurrent_streams():
     assert (counts_np(out) == 6 * expect).all()
 
 
+def test_side_stream_without_out():
+    """A launch on another stream without `out`: the zeroed counters the binding
+    allocates on the current stream are ready before the count adds into them,
+    also while the current stream is still busy."""
+    k, n = 16, 4_000_037
+    host = host_bytes(2 * n, I.Dist.bernoulli(0.6), SEED + 12)
+    expect = oracle_counts(host, n, k)
+    buf, o = to_device(host, 3)
+    side = torch.cuda.Stream()
+    busy = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    for _ in range(3):
+        busy.fill_(1)  # keeps the current stream occupied while the side launch is queued
+        got = api.pospopcnt(buf, k, n=n, byte_offset=o, stream=side)
+        side.synchronize()
+        assert (counts_np(got) == expect).all()
+        got = api.pospopcnt(buf, k, n=n, byte_offset=o, stream=side.cuda_stream)
+        side.synchronize()
+        assert (counts_np(got) == expect).all()
+    torch.cuda.synchronize()
+
+
 def test_zero_length_launches_nothing():
     out = torch.full((16,), 5, dtype=torch.int64, device="cuda")
     buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
