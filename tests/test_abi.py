@@ -243,3 +243,30 @@ def test_header_is_strict_c99_and_callable_from_c():
     mod.check_header_c99()
     res = subprocess.run([_c_caller(), "cpu"], capture_output=True, text=True, timeout=60)
     assert res.returncode == 0, res.stdout + res.stderr
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library every entry point raises ImportError naming the
+    build command: the binding has no CPU fallback.  Run in a fresh interpreter, with
+    the loader pointed at a path that does not exist."""
+    import sys
+    code = "\n".join([
+        "import sys",
+        f"sys.path.insert(0, {ROOT!r})",
+        "from paper_1911_02696_amd import _lib as L",
+        f"L.LIB_PATH = {str(tmp_path / 'libpospopcnt.so')!r}",
+        "from paper_1911_02696_amd import api, batch, serve",
+        "calls = [lambda: api.pospopcnt_ptr(0, 0, 16, 0), lambda: api.device_info(),",
+        "         lambda: batch.Plan(4), lambda: serve.Server(1 << 20), L.lib]",
+        "for call in calls:",
+        "    try:",
+        "        call()",
+        "    except ImportError as e:",
+        "        assert 'is missing' in str(e) and 'build' in str(e), e",
+        "    else:",
+        "        sys.exit('no error raised')",
+        "print('all raised')",
+    ])
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "all raised" in r.stdout
