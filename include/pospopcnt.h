@@ -48,7 +48,9 @@ enum {
     PPC_ERR_BUDGET = 6,   /* serving: request larger than the memory budget */
     PPC_ERR_ARG = 7,      /* another argument is out of range (configuration, size) */
     PPC_ERR_OVERLAP = 8,  /* counts overlaps the input bytes */
-    PPC_ERR_STATE = 9     /* object used in a state that does not allow the call */
+    PPC_ERR_STATE = 9,    /* object used in a state that does not allow the call */
+    PPC_ERR_CAPACITY = 10 /* a fixed capacity of the library is exceeded (see
+                             pospopcnt_batch_static) */
 };
 
 /* Human-readable name of a status code (static storage, never NULL). */
@@ -258,6 +260,31 @@ int ppc_plan_load(ppc_plan* plan, const char* path);
 /* Number of descriptors the last completed pospopcnt_batch call on this plan
  * skipped as invalid.  Enqueues a 4-byte copy on stream and waits for it. */
 int ppc_plan_rejected(ppc_plan* plan, ppc_stream stream, uint32_t* rejected);
+
+/* For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The batched count of
+ * pospopcnt_batch without a plan: the same kernels, with their scratch (prefix
+ * array, per-block start table, preparation partials) in one file-scope device
+ * array of the library, about 530 KiB, which each device holds from the first
+ * call on it until the process ends.  Nothing is allocated, by this call or by
+ * its kernels.
+ *   d_descs  device array of m descriptors, as for pospopcnt_batch; invalid
+ *            descriptors are skipped (their number is not reported).
+ *   m        0 .. PPC_STATIC_MAX_STREAMS; more returns PPC_ERR_CAPACITY and
+ *            launches nothing.
+ *   config   launch configuration (as for ppc_plan_set_config), or NULL for the
+ *            plan's default; blocks_per_cu x compute units may not exceed 4096
+ *            (PPC_ERR_CAPACITY).  No graph, no autotuning.
+ * The first call on a device looks the array's address up (a runtime query, no
+ * allocation); make that call outside stream capture if the capture mode
+ * forbids such queries.  Every call on a device shares that device's array:
+ * calls on one device must not overlap in time (enqueue them on one stream, or
+ * order the streams); overlapping calls race and give wrong counts.
+ * Errors: PPC_ERR_NULL, PPC_ERR_ALIGN, PPC_ERR_CAPACITY, PPC_ERR_ARG (config),
+ * PPC_ERR_HIP. */
+#define PPC_STATIC_MAX_STREAMS 65536
+int pospopcnt_batch_static(const ppc_desc* d_descs, uint32_t m, const ppc_batch_config* config,
+                           ppc_stream stream);
 
 /* One single-stream launch per descriptor, from a HOST array of m descriptors
  * (each launch as pospopcnt with default configuration).  The per-launch form

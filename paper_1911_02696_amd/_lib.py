@@ -16,7 +16,7 @@ PPC_OK = 0
 STATUS_NAMES = {
     0: "PPC_OK", 1: "PPC_ERR_NULL", 2: "PPC_ERR_ALIGN", 3: "PPC_ERR_WIDTH",
     4: "PPC_ERR_RANGE", 5: "PPC_ERR_HIP", 6: "PPC_ERR_BUDGET", 7: "PPC_ERR_ARG",
-    8: "PPC_ERR_OVERLAP", 9: "PPC_ERR_STATE",
+    8: "PPC_ERR_OVERLAP", 9: "PPC_ERR_STATE", 10: "PPC_ERR_CAPACITY",
 }
 VARIANT_CSA, VARIANT_BALLOT, VARIANT_HYBRID = 0, 1, 2
 
@@ -54,6 +54,7 @@ class WorkloadHint(ctypes.Structure):
 
 
 PLAN_GRAPH = 1
+STATIC_MAX_STREAMS = 65536  # PPC_STATIC_MAX_STREAMS
 
 _vp, _u64, _i32, _i64 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64
 _u32 = ctypes.c_uint32
@@ -85,6 +86,7 @@ SIGNATURES = {
     "ppc_plan_load": (_i32, [_vp, ctypes.c_char_p]),
     "ppc_plan_rejected": (_i32, [_vp, _vp, ctypes.POINTER(_u32)]),
     "pospopcnt_each": (_i32, [_vp, _u32, _vp]),
+    "pospopcnt_batch_static": (_i32, [_vp, _u32, ctypes.POINTER(BatchConfig), _vp]),
     "ppc_histogram_u8": (_i32, [_vp, _u64, _u32, _vp, _vp]),
     "ppc_histogram_u16": (_i32, [_vp, _u64, _u32, _vp, _vp]),
     "ppc_histogram_ex": (_i32, [_vp, _u64, _i32, _u32, _vp, _vp, ctypes.POINTER(LaunchConfig)]),

@@ -123,6 +123,27 @@ class Plan:
         return out.value
 
 
+def batch_static(descs: torch.Tensor, m: int | None = None, config: dict | None = None,
+                 stream=None) -> None:
+    """The batched count without a plan (pospopcnt_batch_static): scratch in the
+    library's file-scope device array, nothing allocated.  At most
+    STATIC_MAX_STREAMS descriptors; calls on one device must not overlap in time.
+    config: a dict of the plan configuration's fields, or None for the default."""
+    ptr, m = Plan._descs(descs, m)
+    Plan._keep(descs, stream)
+    cfg = None
+    if config is not None:
+        c = dict(depth=16, block_threads=64, blocks_per_cu=4, stream_weight=4096)
+        c.update(config)
+        cfg = ctypes.byref(BatchConfig(c["depth"], c["block_threads"], c["blocks_per_cu"],
+                                       c["stream_weight"]))
+    check(L.lib().pospopcnt_batch_static(ptr, m, cfg, stream_handle(stream)),
+          "pospopcnt_batch_static")
+
+
+STATIC_MAX_STREAMS = L.STATIC_MAX_STREAMS
+
+
 def pospopcnt_each(host_descs: np.ndarray, stream=None) -> None:
     """One single-stream launch per descriptor of a host table."""
     d = np.ascontiguousarray(host_descs, dtype=np.uint64)

@@ -98,6 +98,8 @@ const char* ppc_status_string(int status) {
     case PPC_ERR_ARG: return "PPC_ERR_ARG: argument out of range";
     case PPC_ERR_OVERLAP: return "PPC_ERR_OVERLAP: counts overlaps the input";
     case PPC_ERR_STATE: return "PPC_ERR_STATE: call not allowed in the object's state";
+    case PPC_ERR_CAPACITY:
+        return "PPC_ERR_CAPACITY: more than the library's fixed capacity (streams or blocks)";
     default: return "unknown pospopcnt status";
     }
 }

@@ -38,6 +38,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -556,31 +557,90 @@ static int check_config(const ppc_batch_config& c) {
     return PPC_OK;
 }
 
-static int enqueue(ppc_plan* pl, const ppc_desc* descs, uint32_t m, hipStream_t s,
-                   unsigned long long* sink, int zero_counts = 0, uint32_t max_blocks = 0) {
-    const ppc_batch_config& c = pl->cfg;
-    uint32_t G = (uint32_t)(c.blocks_per_cu * pl->cus);
+// Device scratch of one batched call: the prefix array cum[m+1], the per-block
+// start table first[G], the rejected count, and the chunk weights and rejected
+// counts of the split preparation (above kPrepLdsPositions streams).
+struct BatchScratch {
+    uint64_t* cum;
+    uint32_t* first;
+    uint32_t* rejected;
+    uint64_t* part;
+    uint32_t* part_bad;
+};
+
+// Enqueues the preparation and the persistent kernel of one batched call on s,
+// with the grid of c (cut to max_blocks when that is not 0).
+static int enqueue_with(const BatchScratch& sc, const ppc_batch_config& c, int cus,
+                        const ppc_desc* descs, uint32_t m, hipStream_t s,
+                        unsigned long long* sink, int zero_counts, uint32_t max_blocks) {
+    uint32_t G = (uint32_t)(c.blocks_per_cu * cus);
     if (max_blocks && max_blocks < G) G = max_blocks;
     uint64_t weight = (uint64_t)c.stream_weight;
+    uint64_t* cum_w = sc.cum;
+    uint32_t* first_w = sc.first;
+    uint32_t* rej = sc.rejected;
     if (m <= kPrepLdsPositions) {
-        void* pargs[] = {(void*)&descs, &m,       &weight,       &pl->cum,
-                         &pl->first,    &G,       &pl->rejected, &zero_counts};
+        void* pargs[] = {(void*)&descs, &m, &weight, &cum_w, &first_w, &G, &rej, &zero_counts};
         PPC_HIP(hipLaunchKernel((const void*)batch_prep, dim3(1), dim3(kPrepThreads), pargs, 0, s));
     } else {
         uint32_t chunks = (m + kChunk - 1) / kChunk;
-        void* a1[] = {(void*)&descs, &m, &weight, &pl->cum, &pl->part, &pl->part_bad, &zero_counts};
+        uint64_t* part_w = sc.part;
+        uint32_t* bad_w = sc.part_bad;
+        void* a1[] = {(void*)&descs, &m, &weight, &cum_w, &part_w, &bad_w, &zero_counts};
         PPC_HIP(hipLaunchKernel((const void*)prep_chunks, dim3(chunks), dim3(kPrepThreads), a1, 0, s));
-        const uint64_t* part = pl->part;
-        const uint32_t* part_bad = pl->part_bad;
-        void* a2[] = {&m, &pl->cum, (void*)&part, (void*)&part_bad, &chunks, &pl->first, &G,
-                      &pl->rejected};
+        const uint64_t* part = sc.part;
+        const uint32_t* part_bad = sc.part_bad;
+        void* a2[] = {&m, &cum_w, (void*)&part, (void*)&part_bad, &chunks, &first_w, &G, &rej};
         PPC_HIP(hipLaunchKernel((const void*)prep_finish, dim3(chunks), dim3(kPrepThreads), a2, 0,
                                 s));
     }
-    const uint64_t* cum = pl->cum;
-    const uint32_t* first = pl->first;
+    const uint64_t* cum = sc.cum;
+    const uint32_t* first = sc.first;
     void* margs[] = {(void*)&descs, (void*)&cum, (void*)&first, &weight, &sink, &m};
     PPC_HIP(hipLaunchKernel(main_kernel(c.depth), dim3(G), dim3(c.block_threads), margs, 0, s));
+    return PPC_OK;
+}
+
+static int enqueue(ppc_plan* pl, const ppc_desc* descs, uint32_t m, hipStream_t s,
+                   unsigned long long* sink, int zero_counts = 0, uint32_t max_blocks = 0) {
+    const BatchScratch sc{pl->cum, pl->first, pl->rejected, pl->part, pl->part_bad};
+    return enqueue_with(sc, pl->cfg, pl->cus, descs, m, s, sink, zero_counts, max_blocks);
+}
+
+// ---- the batched count without a plan: scratch in a file-scope device array
+//
+// Layout of `scratch` (each part 256-byte aligned): cum[PPC_STATIC_MAX_STREAMS + 1],
+// first[kStaticMaxBlocks], the rejected count, and the split preparation's chunk
+// weights and rejected counts.  The preparation kernels write every entry a call
+// reads before the persistent kernel reads it, so nothing needs clearing between
+// calls.
+constexpr uint32_t kStaticMaxBlocks = 4096;  // 16 blocks per CU on 256 CUs
+constexpr uint32_t kStaticChunks = (PPC_STATIC_MAX_STREAMS + kChunk - 1) / kChunk;
+constexpr size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kStaticCumOff = 0;
+constexpr size_t kStaticFirstOff = round256(((size_t)PPC_STATIC_MAX_STREAMS + 1) * 8);
+constexpr size_t kStaticRejOff = kStaticFirstOff + round256((size_t)kStaticMaxBlocks * 4);
+constexpr size_t kStaticPartOff = kStaticRejOff + 256;
+constexpr size_t kStaticPartBadOff = kStaticPartOff + round256((size_t)kStaticChunks * 8);
+constexpr size_t kStaticBytes = kStaticPartBadOff + round256((size_t)kStaticChunks * 4);
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+// The device address of `scratch` on device dev (each device holds its own copy),
+// looked up once per device with that device current.  On the host the array's
+// name is not a device address; only this pointer is passed to kernels.
+static int static_scratch(int dev, char** out) {
+    static std::mutex mu;
+    static char* addr[64] = {};
+    if (dev < 0 || dev >= 64) return PPC_ERR_ARG;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        PPC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return PPC_ERR_HIP;
+        addr[dev] = (char*)p;
+    }
+    *out = addr[dev];
     return PPC_OK;
 }
 
@@ -752,6 +812,26 @@ int pospopcnt_batch(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, ppc_strea
     }
     PPC_HIP(hipGraphLaunch(pl->exec, s));
     return PPC_OK;
+}
+
+int pospopcnt_batch_static(const ppc_desc* d_descs, uint32_t m, const ppc_batch_config* config,
+                           ppc_stream stream) {
+    if (m == 0) return PPC_OK;
+    if (!d_descs) return PPC_ERR_NULL;
+    if ((uintptr_t)d_descs & 7u) return PPC_ERR_ALIGN;
+    if (m > PPC_STATIC_MAX_STREAMS) return PPC_ERR_CAPACITY;
+    const ppc_batch_config c = config ? *config : default_config();
+    int st = check_config(c);
+    if (st) return st;
+    const DeviceFacts* dev = nullptr;
+    if ((st = current_device(&dev))) return st;
+    if ((int64_t)c.blocks_per_cu * dev->cus > (int64_t)kStaticMaxBlocks) return PPC_ERR_CAPACITY;
+    char* base = nullptr;
+    if ((st = static_scratch(dev->device, &base))) return st;
+    const BatchScratch sc{(uint64_t*)(base + kStaticCumOff), (uint32_t*)(base + kStaticFirstOff),
+                          (uint32_t*)(base + kStaticRejOff), (uint64_t*)(base + kStaticPartOff),
+                          (uint32_t*)(base + kStaticPartBadOff)};
+    return enqueue_with(sc, c, dev->cus, d_descs, m, (hipStream_t)stream, nullptr, 0, 0);
 }
 
 int ppc_plan_get_config(const ppc_plan* pl, ppc_batch_config* c) {

@@ -48,7 +48,7 @@ static int cpu_checks(void) {
     EXPECT(ppc_histogram_u8(NULL, 10, 8, fake_counts, NULL) == PPC_ERR_NULL);
     EXPECT(ppc_histogram_u8((const void*)0x1000, 10, 33, fake_counts, NULL) == PPC_ERR_WIDTH);
     EXPECT(ppc_histogram_u8((const void*)0x1000, 10, 0, fake_counts, NULL) == PPC_ERR_WIDTH);
-    for (int st = 0; st <= 9; ++st) {
+    for (int st = 0; st <= 10; ++st) {
         const char* s = ppc_status_string(st);
         EXPECT(s != NULL && strlen(s) > 0);
     }

@@ -198,6 +198,19 @@ def test_batch_arguments(lib):
         assert lib.pospopcnt_each(d.ctypes.data, 2, None) == status, (field, value)
 
 
+def test_static_batch_arguments(lib):
+    """pospopcnt_batch_static validates before any device call: no descriptors, a
+    misaligned table, more streams than its fixed scratch holds, a bad config."""
+    assert lib.pospopcnt_batch_static(None, 0, None, None) == 0
+    assert lib.pospopcnt_batch_static(None, 5, None, None) == 1
+    assert lib.pospopcnt_batch_static(0x1004, 5, None, None) == 2
+    assert lib.pospopcnt_batch_static(0x1000, L.STATIC_MAX_STREAMS + 1, None, None) == 10
+    bad = L.BatchConfig(12, 64, 4, 4096)  # no kernel for 12-dword circuits
+    assert lib.pospopcnt_batch_static(0x1000, 5, ctypes.byref(bad), None) == 7
+    bad = L.BatchConfig(16, 64, 0, 4096)
+    assert lib.pospopcnt_batch_static(0x1000, 5, ctypes.byref(bad), None) == 7
+
+
 def test_plan_needs_a_device(lib):
     import torch
     if torch.cuda.is_available():
