@@ -49,8 +49,10 @@ enum {
     PPC_ERR_ARG = 7,      /* another argument is out of range (configuration, size) */
     PPC_ERR_OVERLAP = 8,  /* counts overlaps the input bytes */
     PPC_ERR_STATE = 9,    /* object used in a state that does not allow the call */
-    PPC_ERR_CAPACITY = 10 /* a fixed capacity of the library is exceeded (see
-                             pospopcnt_batch_static) */
+    PPC_ERR_CAPACITY = 10, /* a fixed capacity of the library is exceeded (see
+                              pospopcnt_batch_static) */
+    PPC_ERR_TIMEOUT = 11,  /* serving: the request waited longer than its timeout */
+    PPC_ERR_CANCELLED = 12 /* serving: the request was cancelled before its launch */
 };
 
 /* Human-readable name of a status code (static storage, never NULL). */
@@ -300,8 +302,10 @@ int pospopcnt_each(const ppc_desc* h_descs, uint32_t m, ppc_stream stream);
  * Requests name a stream already in device memory (src, n, k).  The server
  * admits them in arrival order while its memory budget and request slots allow:
  * an admitted request gets a slab of its input size in the server's device
- * arena, its bytes are copied there (unless PPC_SERVE_IN_PLACE), and it joins the
- * next launch.  Each progress step reaps finished launches (their slabs and
+ * arena and joins the next launch.  Unless PPC_SERVE_IN_PLACE, its bytes are
+ * copied into the slab by the count itself (each input byte is read once and
+ * stored once); the copy starts (src mod 16) bytes into the slab, which is sized
+ * for that.  Each progress step reaps finished launches (their slabs and
  * slots free up), admits waiting requests and launches every newly admitted one
  * as one batched count on the next of the server's HIP streams, so launches
  * overlap on the device while earlier ones still run.  Counts come back to the
@@ -332,21 +336,31 @@ typedef struct {
     double arrival;     /* arrival time in seconds (server clock for ppc_server_submit,
                            offset from the start of the replay for ppc_server_run_trace) */
     uint64_t tag;       /* caller's identifier, returned with the completion */
+    double timeout;     /* seconds after arrival by which the request must be admitted;
+                           a request still waiting then completes with PPC_ERR_TIMEOUT
+                           and is never counted.  0 = no limit (negative or NaN:
+                           PPC_ERR_ARG) */
 } ppc_request;
 
 typedef struct {
     uint64_t tag;
     int32_t status;     /* PPC_OK, PPC_ERR_BUDGET (larger than the arena), PPC_ERR_WIDTH,
-                           PPC_ERR_NULL, PPC_ERR_ARG, or PPC_ERR_HIP if its launch failed */
+                           PPC_ERR_NULL, PPC_ERR_ARG, PPC_ERR_TIMEOUT, PPC_ERR_CANCELLED,
+                           or PPC_ERR_HIP if its launch failed */
     uint32_t batch;     /* requests in the launch that counted it */
     double arrival, admitted, launched, completed;  /* server clock, seconds */
     uint64_t counts[32];                            /* first k entries used */
+    uint64_t arena_offset; /* where the request's bytes were in the arena (copy mode: the
+                              copy's first byte; in place: the reserved slab), UINT64_MAX
+                              if it was never launched.  The slab is free again once the
+                              completion is reported. */
 } ppc_completion;
 
 typedef struct {
     uint64_t submitted, admitted, completed, rejected, launches;
     uint64_t queued_now, inflight_now, max_queued, max_inflight;
     uint64_t arena_used_now, arena_peak, bytes_counted;
+    uint64_t expired, cancelled; /* completed with PPC_ERR_TIMEOUT / PPC_ERR_CANCELLED */
 } ppc_server_stats;
 
 /* Executor callbacks, for driving the scheduler with something other than the
@@ -375,7 +389,12 @@ typedef struct ppc_server ppc_server;
 
 /* Creates a server on the current device: allocates the arena, the streams, one
  * plan per stream and pinned staging for launches (the only serving call that
- * allocates).  Errors: PPC_ERR_NULL, PPC_ERR_ARG, PPC_ERR_HIP. */
+ * allocates).  Errors: PPC_ERR_NULL, PPC_ERR_ARG, PPC_ERR_HIP.
+ * Fault injection for tests: with the environment variable PPC_FAULT_LAUNCH=N
+ * set when the server is created, its N-th launch (counted from 1) fails with
+ * PPC_ERR_HIP after its count was enqueued, as a failed copy of its results
+ * would; the launch's requests complete with that status and the server goes
+ * on serving. */
 int ppc_server_create(const ppc_server_config* config, ppc_server** server);
 
 /* Same scheduler over caller-supplied executor callbacks (no device memory is
@@ -404,6 +423,17 @@ int ppc_server_take_completions(ppc_server* server, ppc_completion* out, uint32_
                                 uint32_t* n_out);
 
 int ppc_server_get_stats(const ppc_server* server, ppc_server_stats* stats);
+
+/* Cancels every request with this tag that is waiting or admitted but not yet
+ * launched: each completes with PPC_ERR_CANCELLED (an admitted one gives its
+ * slab back).  A launched request is not stopped; it completes as usual.
+ * *cancelled (optional) receives how many were cancelled. */
+int ppc_server_cancel(ppc_server* server, uint64_t tag, uint32_t* cancelled);
+
+/* The server's device arena: *base its device address (NULL in place, where no
+ * arena memory is allocated, and for callback executors) and *bytes its size.
+ * Completions give each request's offset in it. */
+int ppc_server_arena(const ppc_server* server, void** base, uint64_t* bytes);
 
 /* Replays n requests in real time: request i is submitted when
  * (now - start) >= requests[i].arrival (arrivals must be non-decreasing), and

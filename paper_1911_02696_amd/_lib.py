@@ -16,7 +16,8 @@ PPC_OK = 0
 STATUS_NAMES = {
     0: "PPC_OK", 1: "PPC_ERR_NULL", 2: "PPC_ERR_ALIGN", 3: "PPC_ERR_WIDTH",
     4: "PPC_ERR_RANGE", 5: "PPC_ERR_HIP", 6: "PPC_ERR_BUDGET", 7: "PPC_ERR_ARG",
-    8: "PPC_ERR_OVERLAP", 9: "PPC_ERR_STATE", 10: "PPC_ERR_CAPACITY",
+    8: "PPC_ERR_OVERLAP", 9: "PPC_ERR_STATE", 10: "PPC_ERR_CAPACITY", 11: "PPC_ERR_TIMEOUT",
+    12: "PPC_ERR_CANCELLED",
 }
 VARIANT_CSA, VARIANT_BALLOT, VARIANT_HYBRID = 0, 1, 2
 

@@ -100,6 +100,8 @@ const char* ppc_status_string(int status) {
     case PPC_ERR_STATE: return "PPC_ERR_STATE: call not allowed in the object's state";
     case PPC_ERR_CAPACITY:
         return "PPC_ERR_CAPACITY: more than the library's fixed capacity (streams or blocks)";
+    case PPC_ERR_TIMEOUT: return "PPC_ERR_TIMEOUT: the request waited longer than its timeout";
+    case PPC_ERR_CANCELLED: return "PPC_ERR_CANCELLED: the request was cancelled before its launch";
     default: return "unknown pospopcnt status";
     }
 }

@@ -382,8 +382,11 @@ prep_finish(uint32_t m, uint64_t* cum, const uint64_t* __restrict__ part,
 // The block's share [lo, hi) of the axis: every stream it touches, from position
 // pos on, counted into the stream's counters (or into sink).  cum: the prefix
 // array, in global memory or in LDS; desc_at(pos): the descriptor at a position.
-template <int LOGD, typename Cum, typename DescAt>
-__device__ __forceinline__ void walk_share(DescAt desc_at, Cum cum,
+// With COPY, dst_at(pos) gives the destination of the stream's bytes (the same
+// address as the source modulo 16): every byte the block reads of the stream is
+// also stored there, so a copy and its count cost one read of the source.
+template <int LOGD, bool COPY, typename Cum, typename DescAt, typename DstAt>
+__device__ __forceinline__ void walk_share(DescAt desc_at, DstAt dst_at, Cum cum,
                                            uint32_t pos, uint32_t m, uint64_t lo, uint64_t hi,
                                            uint64_t weight, unsigned long long* sink,
                                            uint64_t b,
@@ -407,6 +410,8 @@ __device__ __forceinline__ void walk_share(DescAt desc_at, Cum cum,
             const ppc_desc d = desc_at(pos);
             const int k = (int)d.k;
             const DevStream st = split_dev(d.ptr, d.n * (uint64_t)(k / 8), k);
+            intptr_t delta = 0;  // destination - source, a multiple of 16
+            if constexpr (COPY) delta = (intptr_t)dst_at(pos) - (intptr_t)d.ptr;
             const uint64_t bw0 = w0 + weight;  // first body unit of the stream on the axis
             const uint64_t ub = lo > bw0 ? lo - bw0 : 0;
             const uint64_t ue = hi >= w1 ? st.units : (hi > bw0 ? hi - bw0 : 0);
@@ -418,7 +423,7 @@ __device__ __forceinline__ void walk_share(DescAt desc_at, Cum cum,
                 for (int j = 0; j < LOGD; ++j) B[j] = 0;
 #pragma unroll
                 for (int j = 0; j < L; ++j) V[j] = 0;
-                auto consume = [&](const u32x4(&v)[U]) {
+                auto count_tile = [&](const u32x4(&v)[U]) {
                     uint32_t dw[4 * U];
 #pragma unroll
                     for (int j = 0; j < U; ++j) {
@@ -428,6 +433,10 @@ __device__ __forceinline__ void walk_share(DescAt desc_at, Cum cum,
                         dw[4 * j + 3] = v[j].w;
                     }
                     vertical_add<L>(V, Circuit<LOGD>::run(B, dw));
+                };
+                auto consume = [&](const u32x4(&v)[U], const u32x4* at) {
+                    if constexpr (COPY) store_tile<U>(v, at, delta);
+                    count_tile(v);
                 };
                 if (ue > ub) {
                     const u32x4* base = st.body + ub;
@@ -453,12 +462,16 @@ __device__ __forceinline__ void walk_share(DescAt desc_at, Cum cum,
                     }
                     if (rem != 0 && (uint64_t)wave == full % (uint64_t)wpb) {
                         u32x4 t[U];
-                        load_tile_masked<U>(t, base + full * TILE + lane, lane, rem);
-                        consume(t);
+                        const u32x4* at = base + full * TILE + lane;
+                        load_tile_masked<U>(t, at, lane, rem);
+                        if constexpr (COPY) store_tile_masked<U>(t, at, delta, lane, rem);
+                        count_tile(t);
                     }
                 }
                 // running planes (weights 2^j), vertical counter (2^(LOGD + j)), edges (1)
-                const uint32_t e = (own_edges && wave == 0) ? edge_dword(st.edges, lane) : 0u;
+                uint32_t e = 0u;
+                if (own_edges && wave == 0)
+                    e = COPY ? edge_dword_copy(st.edges, lane, delta) : edge_dword(st.edges, lane);
                 uint32_t t[C];
 #pragma unroll
                 for (int i = 0; i < C; ++i) t[i] = __builtin_popcount(e & mask_of<C>(i));
@@ -477,22 +490,37 @@ __device__ __forceinline__ void walk_share(DescAt desc_at, Cum cum,
     }
 }
 
-template <int LOGD>
+// dsts (COPY only): per stream index, where the stream's bytes are copied to.
+template <int LOGD, bool COPY>
 __global__ void __launch_bounds__(kBatchMaxThreads)
-batch_main(const ppc_desc* __restrict__ descs, const uint64_t* __restrict__ cum,
-           const uint32_t* __restrict__ first, uint64_t weight, unsigned long long* sink,
-           uint32_t m) {
+batch_main(const ppc_desc* __restrict__ descs, uint8_t* const* __restrict__ dsts,
+           const uint64_t* __restrict__ cum, const uint32_t* __restrict__ first, uint64_t weight,
+           unsigned long long* sink, uint32_t m) {
     const uint64_t G = gridDim.x, b = blockIdx.x;
     const uint64_t total = cum[m];
     const uint64_t lo = share_lo(b, total, G), hi = share_lo(b + 1, total, G);
     if (lo >= hi) return;  // whole block: no barrier is reached
     __shared__ unsigned long long acc[kBatchMaxThreads / kWave][kBatchClasses];
-    walk_share<LOGD>([&](uint32_t pos) { return descs[stream_at(pos, m)]; }, cum, first[b], m,
-                     lo, hi, weight, sink, b, acc);
+    walk_share<LOGD, COPY>([&](uint32_t pos) { return descs[stream_at(pos, m)]; },
+                           [&](uint32_t pos) { return dsts[stream_at(pos, m)]; }, cum, first[b],
+                           m, lo, hi, weight, sink, b, acc);
 }
 
-static const void* main_kernel(int depth) {
-    return depth == 32 ? (const void*)batch_main<5> : (const void*)batch_main<4>;
+// Circuit depths 4, 8, 16 and 32 dwords per lane (LOGD 2 .. 5).
+static int logd_of(int depth) {
+    return depth == 4 ? 2 : depth == 8 ? 3 : depth == 16 ? 4 : depth == 32 ? 5 : -1;
+}
+
+static const void* main_kernel(int depth, bool copy) {
+    static const void* const plain[4] = {(const void*)batch_main<2, false>,
+                                         (const void*)batch_main<3, false>,
+                                         (const void*)batch_main<4, false>,
+                                         (const void*)batch_main<5, false>};
+    static const void* const copying[4] = {(const void*)batch_main<2, true>,
+                                           (const void*)batch_main<3, true>,
+                                           (const void*)batch_main<4, true>,
+                                           (const void*)batch_main<5, true>};
+    return (copy ? copying : plain)[logd_of(depth) - 2];
 }
 
 // Small batches in one kernel, for callers whose counters are already zero: every
@@ -503,11 +531,13 @@ static const void* main_kernel(int depth) {
 // two kernels.  The descriptors are read once per block, so they may live in
 // pinned host memory (the serving executor's staging buffer).
 
-template <int LOGD>
+template <int LOGD, bool COPY>
 __global__ void __launch_bounds__(kBatchMaxThreads)
-batch_small(const ppc_desc* __restrict__ descs, uint32_t m, uint64_t weight) {
+batch_small(const ppc_desc* __restrict__ descs, uint8_t* const* __restrict__ dsts, uint32_t m,
+            uint64_t weight) {
     __shared__ uint64_t lcum[kSmallBatch + 1];
     __shared__ ppc_desc ldesc[kSmallBatch];  // position order
+    __shared__ uint8_t* ldst[COPY ? kSmallBatch : 1];
     __shared__ uint64_t sh[kBatchMaxThreads / kWave];
     __shared__ unsigned long long acc[kBatchMaxThreads / kWave][kBatchClasses];
     const uint32_t T = blockDim.x, t = threadIdx.x;
@@ -517,8 +547,10 @@ batch_small(const ppc_desc* __restrict__ descs, uint32_t m, uint64_t weight) {
     for (uint32_t r = 0; r < R; ++r) {
         const uint32_t p = t * R + r;
         if (p < m) {
-            const ppc_desc d = descs[stream_at(p, m)];
+            const uint32_t i = stream_at(p, m);
+            const ppc_desc d = descs[i];
             ldesc[p] = d;
+            if constexpr (COPY) ldst[p] = dsts[i];
             const uint64_t w = weight_of(d, weight, &bad);
             lcum[p] = w;
             local += w;
@@ -544,12 +576,25 @@ batch_small(const ppc_desc* __restrict__ descs, uint32_t m, uint64_t weight) {
         const uint32_t mid = l + (h - l) / 2;
         if (lcum[mid] <= lo) l = mid; else h = mid;
     }
-    walk_share<LOGD>([&](uint32_t pos) { return ldesc[pos]; }, (const uint64_t*)lcum, l, m, lo,
-                     hi, weight, nullptr, b, acc);
+    walk_share<LOGD, COPY>([&](uint32_t pos) { return ldesc[pos]; },
+                           [&](uint32_t pos) { return ldst[COPY ? pos : 0]; },
+                           (const uint64_t*)lcum, l, m, lo, hi, weight, nullptr, b, acc);
+}
+
+static const void* small_kernel(int depth, bool copy) {
+    static const void* const plain[4] = {(const void*)batch_small<2, false>,
+                                         (const void*)batch_small<3, false>,
+                                         (const void*)batch_small<4, false>,
+                                         (const void*)batch_small<5, false>};
+    static const void* const copying[4] = {(const void*)batch_small<2, true>,
+                                           (const void*)batch_small<3, true>,
+                                           (const void*)batch_small<4, true>,
+                                           (const void*)batch_small<5, true>};
+    return (copy ? copying : plain)[logd_of(depth) - 2];
 }
 
 static int check_config(const ppc_batch_config& c) {
-    if (c.depth != 16 && c.depth != 32) return PPC_ERR_ARG;
+    if (logd_of(c.depth) < 0) return PPC_ERR_ARG;
     if (c.block_threads != 64 && c.block_threads != 128 && c.block_threads != 256)
         return PPC_ERR_ARG;
     if (c.blocks_per_cu < 1 || c.blocks_per_cu > kMaxBlocksPerCu) return PPC_ERR_ARG;
@@ -570,9 +615,11 @@ struct BatchScratch {
 
 // Enqueues the preparation and the persistent kernel of one batched call on s,
 // with the grid of c (cut to max_blocks when that is not 0).
+// dsts, when not NULL, gives per stream index where its bytes are copied to.
 static int enqueue_with(const BatchScratch& sc, const ppc_batch_config& c, int cus,
                         const ppc_desc* descs, uint32_t m, hipStream_t s,
-                        unsigned long long* sink, int zero_counts, uint32_t max_blocks) {
+                        unsigned long long* sink, int zero_counts, uint32_t max_blocks,
+                        uint8_t* const* dsts = nullptr) {
     uint32_t G = (uint32_t)(c.blocks_per_cu * cus);
     if (max_blocks && max_blocks < G) G = max_blocks;
     uint64_t weight = (uint64_t)c.stream_weight;
@@ -596,15 +643,17 @@ static int enqueue_with(const BatchScratch& sc, const ppc_batch_config& c, int c
     }
     const uint64_t* cum = sc.cum;
     const uint32_t* first = sc.first;
-    void* margs[] = {(void*)&descs, (void*)&cum, (void*)&first, &weight, &sink, &m};
-    PPC_HIP(hipLaunchKernel(main_kernel(c.depth), dim3(G), dim3(c.block_threads), margs, 0, s));
+    void* margs[] = {(void*)&descs, (void*)&dsts, (void*)&cum, (void*)&first, &weight, &sink, &m};
+    PPC_HIP(hipLaunchKernel(main_kernel(c.depth, dsts != nullptr), dim3(G), dim3(c.block_threads),
+                            margs, 0, s));
     return PPC_OK;
 }
 
 static int enqueue(ppc_plan* pl, const ppc_desc* descs, uint32_t m, hipStream_t s,
-                   unsigned long long* sink, int zero_counts = 0, uint32_t max_blocks = 0) {
+                   unsigned long long* sink, int zero_counts = 0, uint32_t max_blocks = 0,
+                   uint8_t* const* dsts = nullptr) {
     const BatchScratch sc{pl->cum, pl->first, pl->rejected, pl->part, pl->part_bad};
-    return enqueue_with(sc, pl->cfg, pl->cus, descs, m, s, sink, zero_counts, max_blocks);
+    return enqueue_with(sc, pl->cfg, pl->cus, descs, m, s, sink, zero_counts, max_blocks, dsts);
 }
 
 // ---- the batched count without a plan: scratch in a file-scope device array
@@ -672,7 +721,7 @@ namespace ppc {
 constexpr uint64_t kFreshUnitsPerWave = 1024;  // 16 KiB of body per wave
 
 int batch_fresh(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s,
-                uint64_t bytes) {
+                uint64_t bytes, uint8_t* const* dsts) {
     if (!pl || !d_descs) return PPC_ERR_NULL;
     if (m == 0) return PPC_OK;
     if (m > pl->max_streams) return PPC_ERR_ARG;
@@ -683,7 +732,7 @@ int batch_fresh(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s
         const uint64_t want = (units + per_block - 1) / per_block;
         max_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 1u << 30);
     }
-    return enqueue(pl, d_descs, m, s, nullptr, 1, max_blocks);
+    return enqueue(pl, d_descs, m, s, nullptr, 1, max_blocks, dsts);
 }
 
 uint32_t small_batch_grid(const ppc_plan* pl, uint32_t m, uint64_t bytes) {
@@ -696,18 +745,18 @@ uint32_t small_batch_grid(const ppc_plan* pl, uint32_t m, uint64_t bytes) {
 }
 
 int batch_zeroed(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, hipStream_t s,
-                 uint64_t bytes) {
+                 uint64_t bytes, uint8_t* const* dsts) {
     if (!pl || !d_descs) return PPC_ERR_NULL;
     // (m <= kSmallBatch: d_descs may be pinned host memory, read once per block)
     if (m == 0) return PPC_OK;
     if (m > pl->max_streams) return PPC_ERR_ARG;
-    if (m > kSmallBatch) return batch_fresh(pl, d_descs, m, s, bytes);
+    if (m > kSmallBatch) return batch_fresh(pl, d_descs, m, s, bytes, dsts);
     const ppc_batch_config& c = pl->cfg;
     const uint32_t G = small_batch_grid(pl, m, bytes);
     uint64_t weight = (uint64_t)c.stream_weight;
-    void* args[] = {(void*)&d_descs, &m, &weight};
-    const void* kern = c.depth == 32 ? (const void*)batch_small<5> : (const void*)batch_small<4>;
-    PPC_HIP(hipLaunchKernel(kern, dim3(G), dim3(c.block_threads), args, 0, s));
+    void* args[] = {(void*)&d_descs, (void*)&dsts, &m, &weight};
+    PPC_HIP(hipLaunchKernel(small_kernel(c.depth, dsts != nullptr), dim3(G), dim3(c.block_threads),
+                            args, 0, s));
     return PPC_OK;
 }
 }  // namespace ppc

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace ppc {
 
 constexpr int kWave = 64;
@@ -246,6 +248,17 @@ __device__ __forceinline__ void load_tile_masked(u32x4 (&v)[U], const u32x4* __r
                                                      : u32x4{0u, 0u, 0u, 0u};
 }
 
+// A tile consumer takes the loaded tile, and also the lane's address of it when
+// it accepts a second argument (the copying consumers store the tile elsewhere).
+template <int U, typename F>
+__device__ __forceinline__ void consume_tile(F& consume, const u32x4 (&v)[U],
+                                             const u32x4* p) {
+    if constexpr (std::is_invocable_v<F&, const u32x4(&)[U], const u32x4*>)
+        consume(v, p);
+    else
+        consume(v);
+}
+
 // Consume `count` whole tiles starting at p (already offset by the lane), each
 // `stride` units after the previous, with two tiles in flight: the next tile's
 // loads are issued before the current tile is consumed.  The trip count is known
@@ -260,19 +273,61 @@ __device__ __forceinline__ void walk_n(const u32x4* __restrict__ p, uint64_t cou
     load_tile<U>(a, p);
     while (count >= 3) {
         load_tile<U>(b, p + stride);
-        consume(a);
+        consume_tile<U>(consume, a, p);
         load_tile<U>(a, p + 2 * stride);
-        consume(b);
+        consume_tile<U>(consume, b, p + stride);
         p += 2 * stride;
         count -= 2;
     }
     if (count == 2) {
         load_tile<U>(b, p + stride);
-        consume(a);
-        consume(b);
+        consume_tile<U>(consume, a, p);
+        consume_tile<U>(consume, b, p + stride);
     } else {
-        consume(a);
+        consume_tile<U>(consume, a, p);
     }
+}
+
+// ---------------------------------------------------------------- copying walks
+//
+// A copying count also writes every byte it reads to a destination that starts
+// at the same address modulo 16 as the source, so that each 16-byte body unit of
+// the source lands on one aligned 16-byte unit of the destination: delta =
+// dst - src is a multiple of 16.  Stores are nontemporal: the copy is not read
+// back by the count.
+typedef __attribute__((address_space(1))) u32x4 global_u32x4_w;
+
+template <int U>
+__device__ __forceinline__ void store_tile(const u32x4 (&v)[U], const u32x4* src_lane,
+                                           intptr_t delta) {
+    u32x4* q = (u32x4*)((const char*)src_lane + delta);
+#pragma unroll
+    for (int j = 0; j < U; ++j) __builtin_nontemporal_store(v[j], (global_u32x4_w*)(q + j * kWave));
+}
+
+// Stores of the masked last tile: only the units below `rem`.
+template <int U>
+__device__ __forceinline__ void store_tile_masked(const u32x4 (&v)[U], const u32x4* src_lane,
+                                                  intptr_t delta, int lane, uint64_t rem) {
+    u32x4* q = (u32x4*)((const char*)src_lane + delta);
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        if ((uint64_t)(j * kWave + lane) < rem)
+            __builtin_nontemporal_store(v[j], (global_u32x4_w*)(q + j * kWave));
+}
+
+// edge_dword, also writing the lane's edge byte (if any) to its place at delta.
+__device__ __forceinline__ uint32_t edge_dword_copy(const Edges& e, int lane, intptr_t delta) {
+    const uint8_t* p = nullptr;
+    if (lane < 16) {
+        if ((uint32_t)lane < e.head_len) p = e.head + lane;
+    } else if (lane < 32) {
+        if ((uint32_t)(lane - 16) < e.tail_len) p = e.tail + (lane - 16);
+    }
+    if (!p) return 0u;
+    const uint8_t byte = *p;
+    *(uint8_t*)(p + delta) = byte;
+    return (uint32_t)byte << (8u * (uint32_t)((uintptr_t)p & 3u));
 }
 
 // Walk this wave's whole tiles t = gw, gw + nw, ... < full of a body.

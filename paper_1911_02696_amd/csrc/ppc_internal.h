@@ -67,8 +67,11 @@ int launch_stream(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stre
 // pospopcnt_batch without graph capture, clearing each valid descriptor's
 // counters before counting (the descriptors must own distinct counters).  bytes:
 // the batch's input bytes if known (sizes the grid for small batches), else 0.
+// dsts: NULL, or per descriptor the address its input bytes are also copied to
+// while they are counted (congruent to the input's address modulo 16, and not
+// overlapping any input or counter); the array lives where descs does.
 int batch_fresh(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, hipStream_t stream,
-                uint64_t bytes);
+                uint64_t bytes, uint8_t* const* dsts = nullptr);
 
 // As batch_fresh for callers whose counters are zero already (the serving
 // executor clears them after reading them back): up to kSmallBatch descriptors run
@@ -76,7 +79,7 @@ int batch_fresh(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, hipStream_t
 // kSmallBatch, descs may also be pinned host memory (each block reads them once).
 constexpr uint32_t kSmallBatch = 1024;
 int batch_zeroed(ppc_plan* plan, const ppc_desc* descs, uint32_t m, hipStream_t stream,
-                 uint64_t bytes);
+                 uint64_t bytes, uint8_t* const* dsts = nullptr);
 // The grid batch_zeroed launches for m <= kSmallBatch descriptors and `bytes` of input.
 uint32_t small_batch_grid(const ppc_plan* plan, uint32_t m, uint64_t bytes);
 // Descriptors a launch may read from pinned host memory, summed over its blocks,

@@ -13,10 +13,11 @@
 //
 // GPU executor: a launch on stream s (launch slots rotate over the streams, two
 // per stream) enqueues, in order: one host-to-device copy of the descriptor table
-// and the copy segments, the copy of every request's input from its source into
-// its slab (one kernel, byte-balanced over its blocks), the batched count (one plan per
-// stream; its prefix kernel clears the launch's counters), the copy of the counts
-// to pinned host memory, and an event the scheduler polls.
+// (and, in copy mode, of where each request's copy goes), unless the launch is
+// small enough for its kernel to read them from pinned host memory; the batched
+// count, which in copy mode also stores every byte it reads into the request's
+// slab, so that each input byte is read once and written once; the copy of the
+// counts to pinned host memory, and an event the scheduler polls.
 #include <string.h>
 
 #include <algorithm>
@@ -90,9 +91,15 @@ class Arena {
 
 // ------------------------------------------------------------------ executors
 
+// In copy mode a request's copy starts at its source's address modulo 16 inside
+// its slab: the slab holds copy_shift(src) + bytes.
+__host__ __device__ inline uint64_t copy_shift(const void* src) { return (uintptr_t)src & 15u; }
+
 struct Admitted {
     ppc_request r;
-    uint64_t bytes, off;
+    uint64_t bytes;  // input bytes
+    uint64_t slab;   // bytes reserved in the arena (input plus the copy's shift)
+    uint64_t off;    // slab offset in the arena
     double admitted;
 };
 
@@ -133,72 +140,16 @@ class CallbackExecutor : public Executor {
     size_t cap_;
 };
 
-// One request's input copy: `units` 16-byte units from src to dst, starting at
-// unit `start` of the launch's copy axis.  When src or dst is not 16-byte
-// aligned the unit is copied byte by byte (never past `bytes`).
-struct CopySeg {
-    const uint8_t* src;
-    uint8_t* dst;
-    uint64_t bytes;
-    uint64_t start;
-};
-
-__device__ __forceinline__ uint64_t seg_units(const CopySeg& s) { return (s.bytes + 15) / 16; }
-
-// Copies every segment of a launch.  Block b takes the b-th of G equal slices of
-// the launch's units (segments laid end to end), so a large request is spread
-// over all blocks and small ones share blocks; each thread keeps four 16-byte
-// loads in flight.  Aligned segments may write the rest of their last unit: the
-// destination slab is rounded up to 256 bytes, and the source unit holding the
-// last byte lies within that byte's page.
-__global__ void __launch_bounds__(256) copy_segments(const CopySeg* __restrict__ segs, uint32_t n,
-                                                     uint64_t total) {
-    const uint64_t G = gridDim.x, b = blockIdx.x, T = blockDim.x;
-    const uint64_t base = total / G, extra = total % G;
-    const uint64_t lo = b * base + (b < extra ? b : extra);
-    const uint64_t hi = lo + base + (b < extra ? 1 : 0);
-    if (lo >= hi) return;
-    uint32_t l = 0, h = n;  // last segment starting at or before lo
-    while (h - l > 1) {
-        const uint32_t mid = l + (h - l) / 2;
-        if (segs[mid].start <= lo) l = mid; else h = mid;
-    }
-    for (uint32_t i = l; i < n; ++i) {
-        const CopySeg sg = segs[i];
-        if (sg.start >= hi) break;
-        const uint64_t units = seg_units(sg);
-        const uint64_t u0 = lo > sg.start ? lo - sg.start : 0;
-        const uint64_t u1 = hi < sg.start + units ? hi - sg.start : units;
-        if (u0 >= u1) continue;
-        if ((((uintptr_t)sg.src | (uintptr_t)sg.dst) & 15u) == 0) {
-            const u32x4* src = (const u32x4*)sg.src;
-            u32x4* dst = (u32x4*)sg.dst;
-            uint64_t u = u0 + threadIdx.x;
-            for (; u + 3 * T < u1; u += 4 * T) {
-                const u32x4 a = stream_load(src + u), c = stream_load(src + u + T),
-                            d = stream_load(src + u + 2 * T), e = stream_load(src + u + 3 * T);
-                dst[u] = a;
-                dst[u + T] = c;
-                dst[u + 2 * T] = d;
-                dst[u + 3 * T] = e;
-            }
-            for (; u < u1; u += T) dst[u] = stream_load(src + u);
-        } else {
-            for (uint64_t u = u0 + threadIdx.x; u < u1; u += T)
-                for (uint64_t x = u * 16; x < u * 16 + 16 && x < sg.bytes; ++x) sg.dst[x] = sg.src[x];
-        }
-    }
-}
-
 class HipExecutor : public Executor {
   public:
-    // One launch's buffers.  Descriptors and copy segments share one staging area
-    // (and one device area) so that a single host-to-device copy carries both.
+    // One launch's buffers.  The descriptors and, in copy mode, the destination of
+    // each request's copy share one staging area (and one device area), so that a
+    // single host-to-device copy carries both.
     struct Slot {
         int stream = 0;
         bool busy = false;
         uint32_t n = 0;
-        char* d_meta = nullptr;  // [descs: max_batch][segments: max_batch]
+        char* d_meta = nullptr;  // [descs: n][destinations: n], each part 256-byte aligned
         uint64_t* d_counts = nullptr;
         char* h_meta = nullptr;
         uint64_t* h_counts = nullptr;
@@ -215,6 +166,9 @@ class HipExecutor : public Executor {
         device_ = dev->device;
         cus_ = dev->cus;
         in_place_ = (c.flags & PPC_SERVE_IN_PLACE) != 0;
+        // Test hook: PPC_FAULT_LAUNCH=N makes the N-th launch (counted from 1) fail
+        // as if its results copy had failed, after its count was enqueued.
+        if (const char* f = getenv("PPC_FAULT_LAUNCH")) fault_launch_ = strtoull(f, nullptr, 10);
         if (!in_place_ && c.arena_bytes) PPC_HIP(hipMalloc(&arena_, c.arena_bytes));
         streams_.resize(c.streams, nullptr);
         plans_.resize(c.streams, nullptr);
@@ -231,8 +185,7 @@ class HipExecutor : public Executor {
             if (st) return st;
         }
         slots_.resize((size_t)c.streams * 2);
-        seg_base_ = (sizeof(ppc_desc) * c.max_batch + 255) & ~(size_t)255;
-        const size_t meta = seg_base_ + (in_place_ ? 0 : sizeof(CopySeg) * c.max_batch);
+        const size_t meta = dst_offset(c.max_batch) + (in_place_ ? 0 : 8ull * c.max_batch);
         for (size_t i = 0; i < slots_.size(); ++i) {
             Slot& s = slots_[i];
             s.stream = (int)(i % c.streams);
@@ -241,12 +194,11 @@ class HipExecutor : public Executor {
             // counters start at zero; each launch clears the ones it used after its
             // results have been copied back (see launch)
             PPC_HIP(hipMemset(s.d_counts, 0, 256ull * c.max_batch));
-            // In place, small launches are read by the counting kernel straight from
-            // this pinned buffer (see launch), which the host rewrites before every
-            // launch of the slot: fine-grained (coherent) memory, so that the device
-            // never holds a stale copy of it.
-            PPC_HIP(hipHostMalloc(&s.h_meta, meta,
-                                  in_place_ ? hipHostMallocCoherent : hipHostMallocDefault));
+            // Small launches are read by the counting kernel straight from this pinned
+            // buffer (see launch), which the host rewrites before every launch of the
+            // slot: fine-grained (coherent) memory, so that the device never holds a
+            // stale copy of it.
+            PPC_HIP(hipHostMalloc(&s.h_meta, meta, hipHostMallocCoherent));
             PPC_HIP(hipHostMalloc(&s.h_counts, 256ull * c.max_batch));
             PPC_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
         }
@@ -275,6 +227,8 @@ class HipExecutor : public Executor {
 
     size_t capacity() const override { return slots_.size(); }
 
+    void* arena() const { return arena_; }
+
     int launch(const std::vector<Admitted>& items, uint64_t* handle) override {
         size_t si = slots_.size();
         for (size_t j = 0; j < slots_.size(); ++j) {
@@ -289,30 +243,28 @@ class HipExecutor : public Executor {
         Slot& s = slots_[si];
         const uint32_t n = (uint32_t)items.size();
         hipStream_t st = streams_[s.stream];
-        // the copy segments follow this batch's descriptors, so that the one
+        // The destinations follow this batch's own descriptors, so that the one
         // host-to-device copy stays small (large ones go through a DMA engine, whose
-        // hand-over to the compute queue costs tens of microseconds)
-        const size_t seg_off = (sizeof(ppc_desc) * n + 255) & ~(size_t)255;
-        CopySeg* h_segs = (CopySeg*)(s.h_meta + seg_off);
-        uint64_t units = 0, bytes = 0;
+        // hand-over to the compute queue costs tens of microseconds).  A request's
+        // copy starts at its source's address modulo 16 inside its slab (the
+        // scheduler sized the slab for that), so the count stores each aligned
+        // 16-byte unit it reads to one aligned unit of the slab.
+        const size_t dst_off = dst_offset(n);
+        uint8_t** h_dsts = (uint8_t**)(s.h_meta + dst_off);
+        uint64_t bytes = 0;
         for (uint32_t i = 0; i < n; ++i) {
             const Admitted& a = items[i];
-            uint8_t* dst = in_place_ ? nullptr : (uint8_t*)arena_ + a.off;
-            if (!in_place_) {
-                h_segs[i] = {(const uint8_t*)a.r.src, dst, a.bytes, units};
-                units += (a.bytes + 15) / 16;
-            }
-            s.h_descs()[i] = {in_place_ ? a.r.src : (const void*)dst, a.r.n, a.r.k, 0,
-                              s.d_counts + 32ull * i};
+            if (!in_place_) h_dsts[i] = (uint8_t*)arena_ + a.off + copy_shift(a.r.src);
+            s.h_descs()[i] = {a.r.src, a.r.n, a.r.k, 0, s.d_counts + 32ull * i};
             bytes += a.bytes;
         }
-        // One copy of the descriptors (and the copy segments right after them), except
-        // in place for launches small enough for the counting kernel to read the
-        // descriptors from the pinned buffer itself, every block once (kDirectReads
-        // descriptors in all at most): that saves the copy and the queue's gap after it.
-        const bool direct =
-            in_place_ && n <= kSmallBatch &&
-            (uint64_t)small_batch_grid(plans_[s.stream], n, bytes) * n <= kDirectReads;
+        // One copy of the descriptors (and the destinations right after them), except
+        // for launches small enough for the counting kernel to read them from the
+        // pinned buffer itself, every block once (kDirectReads descriptors in all at
+        // most): that saves the copy and the queue's gap after it.
+        const bool direct = n <= kSmallBatch &&
+                            (uint64_t)small_batch_grid(plans_[s.stream], n, bytes) * n <=
+                                kDirectReads;
         // A failure once work is queued: wait for that work, so that no kernel still
         // writes into the slabs the scheduler frees when it fails these requests, and
         // clear the counters it may have added to, which the slot's next launch
@@ -329,22 +281,15 @@ class HipExecutor : public Executor {
         if (e_ != hipSuccess) return abandon(::ppc::fail_hip(e_)); \
     } while (0)
         if (!direct) {
-            const size_t meta = in_place_ ? sizeof(ppc_desc) * n : seg_off + sizeof(CopySeg) * n;
+            const size_t meta = in_place_ ? sizeof(ppc_desc) * n : dst_off + 8ull * n;
             PPC_HIP_QUEUED(hipMemcpyAsync(s.d_meta, s.h_meta, meta, hipMemcpyHostToDevice, st));
         }
-        if (units) {
-            const CopySeg* d_segs = (const CopySeg*)(s.d_meta + seg_off);
-            // about 16 KiB per block, at most 8 blocks per compute unit
-            const uint64_t want = (units + 1023) / 1024;
-            const uint32_t grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)cus_ * 8);
-            void* args[] = {(void*)&d_segs, (void*)&n, &units};
-            PPC_HIP_QUEUED(
-                hipLaunchKernel((const void*)copy_segments, dim3(grid), dim3(256), args, 0, st));
-        }
+        char* meta = direct ? s.h_meta : s.d_meta;
+        uint8_t* const* dsts = in_place_ ? nullptr : (uint8_t* const*)(meta + dst_off);
         // the slot's counters are zero here (cleared after the slot's previous use)
-        const int bst =
-            batch_zeroed(plans_[s.stream], direct ? s.h_descs() : s.d_descs(), n, st, bytes);
+        const int bst = batch_zeroed(plans_[s.stream], (const ppc_desc*)meta, n, st, bytes, dsts);
         if (bst) return abandon(bst);
+        if (++launches_ == fault_launch_) return abandon(fail_hip(hipErrorLaunchFailure));
         PPC_HIP_QUEUED(
             hipMemcpyAsync(s.h_counts, s.d_counts, 256ull * n, hipMemcpyDeviceToHost, st));
         PPC_HIP_QUEUED(hipEventRecord(s.done, st));
@@ -380,11 +325,13 @@ class HipExecutor : public Executor {
     }
 
   private:
+    static size_t dst_offset(uint32_t n) { return (sizeof(ppc_desc) * n + 255) & ~(size_t)255; }
+
     ppc_server_config cfg_{};
     int device_ = -1, cus_ = 0;
     bool in_place_ = false;
     void* arena_ = nullptr;
-    size_t seg_base_ = 0;
+    uint64_t launches_ = 0, fault_launch_ = 0;
     std::vector<hipStream_t> streams_;
     std::vector<ppc_plan*> plans_;
     std::vector<Slot> slots_;
@@ -411,14 +358,16 @@ struct ppc_server {
     };
     struct Waiting {
         ppc_request r;
-        uint64_t bytes;
+        uint64_t bytes, slab;
     };
 
     ppc_server_config cfg{};
     std::unique_ptr<Executor> exec;
+    void* arena_base = nullptr;  // the executor's device arena (NULL in place or virtual)
     Arena arena{0};
     std::deque<Waiting> queue;
-    std::vector<Admitted> admitted;  // admitted, not yet launched
+    uint64_t queued_with_timeout = 0;  // waiting requests that carry a timeout
+    std::vector<Admitted> admitted;    // admitted, not yet launched
     std::vector<Inflight> inflight;
     std::deque<ppc_completion> done;
     uint64_t slots = 0;  // requests admitted and not yet completed
@@ -430,8 +379,15 @@ struct ppc_server {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
 
+    bool copies() const { return (cfg.flags & PPC_SERVE_IN_PLACE) == 0; }
+
+    // Slab of a request: its bytes, plus in copy mode the shift of its copy.
+    uint64_t slab_of(const ppc_request& r, uint64_t bytes) const {
+        return bytes + (copies() ? copy_shift(r.src) : 0);
+    }
+
     void complete(const ppc_request& r, int status, uint32_t batch, double admitted_t,
-                  double launched_t, const uint64_t* c) {
+                  double launched_t, const uint64_t* c, uint64_t arena_off = UINT64_MAX) {
         ppc_completion x;
         memset(&x, 0, sizeof(x));
         x.tag = r.tag;
@@ -442,8 +398,15 @@ struct ppc_server {
         x.launched = launched_t;
         x.completed = now();
         if (c && status == PPC_OK) memcpy(x.counts, c, sizeof(uint64_t) * r.k);
+        x.arena_offset = arena_off;
         done.push_back(x);
         ++stats.completed;
+    }
+
+    // Where the request's bytes sit in the arena: the copy's first byte in copy
+    // mode, the reserved slab in place.
+    uint64_t copy_offset(const Admitted& a) const {
+        return a.off + (copies() ? copy_shift(a.r.src) : 0);
     }
 
     void finish(Inflight& f, int status) {
@@ -454,8 +417,9 @@ struct ppc_server {
         }
         for (uint32_t i = 0; i < n; ++i) {
             const Admitted& a = f.items[i];
-            complete(a.r, status, n, a.admitted, f.launched, status ? nullptr : &counts[32ull * i]);
-            arena.release(a.off, a.bytes);
+            complete(a.r, status, n, a.admitted, f.launched, status ? nullptr : &counts[32ull * i],
+                     copy_offset(a));
+            arena.release(a.off, a.slab);
             if (!status) stats.bytes_counted += a.bytes;
         }
         slots -= n;
@@ -478,13 +442,34 @@ struct ppc_server {
         return n;
     }
 
+    // Waiting requests whose timeout has passed complete with PPC_ERR_TIMEOUT.
+    uint32_t expire() {
+        if (!queued_with_timeout) return 0;
+        const double t = now();
+        uint32_t n = 0;
+        for (auto it = queue.begin(); it != queue.end();) {
+            const ppc_request& r = it->r;
+            if (r.timeout > 0 && t > r.arrival + r.timeout) {
+                complete(r, PPC_ERR_TIMEOUT, 0, 0.0, 0.0, nullptr);
+                ++stats.expired;
+                --queued_with_timeout;
+                ++n;
+                it = queue.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        return n;
+    }
+
     void admit() {
         const double t = now();
         const bool bypass = (cfg.flags & PPC_SERVE_FIFO_BYPASS) != 0;
         for (auto it = queue.begin(); it != queue.end() && slots < cfg.max_requests;) {
             uint64_t off = 0;
-            if (arena.alloc(it->bytes, &off)) {
-                admitted.push_back({it->r, it->bytes, off, t});
+            if (arena.alloc(it->slab, &off)) {
+                admitted.push_back({it->r, it->bytes, it->slab, off, t});
+                if (it->r.timeout > 0) --queued_with_timeout;
                 ++slots;
                 ++stats.admitted;
                 it = queue.erase(it);
@@ -494,6 +479,35 @@ struct ppc_server {
                 break;
             }
         }
+    }
+
+    // Requests with this tag that have not been launched complete with
+    // PPC_ERR_CANCELLED (an admitted one gives its slab back).
+    uint32_t cancel(uint64_t tag) {
+        uint32_t n = 0;
+        for (auto it = queue.begin(); it != queue.end();) {
+            if (it->r.tag == tag) {
+                if (it->r.timeout > 0) --queued_with_timeout;
+                complete(it->r, PPC_ERR_CANCELLED, 0, 0.0, 0.0, nullptr);
+                ++n;
+                it = queue.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        for (auto it = admitted.begin(); it != admitted.end();) {
+            if (it->r.tag == tag) {
+                complete(it->r, PPC_ERR_CANCELLED, 0, it->admitted, 0.0, nullptr);
+                arena.release(it->off, it->slab);
+                --slots;
+                ++n;
+                it = admitted.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        stats.cancelled += n;
+        return n;
     }
 
     uint32_t launch() {
@@ -507,8 +521,8 @@ struct ppc_server {
         ++stats.launches;
         if (st) {
             for (const Admitted& a : f.items) {
-                complete(a.r, st, (uint32_t)n, a.admitted, f.launched, nullptr);
-                arena.release(a.off, a.bytes);
+                complete(a.r, st, (uint32_t)n, a.admitted, f.launched, nullptr, copy_offset(a));
+                arena.release(a.off, a.slab);
             }
             slots -= n;
             return (uint32_t)n;
@@ -544,6 +558,7 @@ int ppc_server_create(const ppc_server_config* config, ppc_server** out) {
     ppc_server* s = new ppc_server();
     s->cfg = *config;
     s->arena = Arena(config->arena_bytes);
+    s->arena_base = ex->arena();
     s->exec = std::move(ex);
     *out = s;
     return PPC_OK;
@@ -578,14 +593,17 @@ int ppc_server_submit(ppc_server* s, const ppc_request* reqs, uint32_t n) {
         const ppc_request& r = reqs[i];
         ++s->stats.submitted;
         int st = PPC_OK;
-        uint64_t bytes = 0;
+        uint64_t bytes = 0, slab = 0;
         if (r.k != 8 && r.k != 16 && r.k != 32) st = PPC_ERR_WIDTH;
         else if (r.reserved) st = PPC_ERR_ARG;
+        else if (!(r.timeout >= 0.0)) st = PPC_ERR_ARG;  // negative or NaN
         else if (r.n > UINT64_MAX / (r.k / 8)) st = PPC_ERR_ARG;
         else if (r.n && !r.src) st = PPC_ERR_NULL;
         else {
             bytes = r.n * (r.k / 8);
-            if (Arena::granules(bytes) > s->arena.size()) st = PPC_ERR_BUDGET;
+            slab = bytes <= s->arena.size() ? s->slab_of(r, bytes) : 0;
+            if (bytes > s->arena.size() || Arena::granules(slab) > s->arena.size())
+                st = PPC_ERR_BUDGET;
         }
         if (st) {
             ++s->stats.rejected;
@@ -594,7 +612,8 @@ int ppc_server_submit(ppc_server* s, const ppc_request* reqs, uint32_t n) {
             static const uint64_t zeros[32] = {0};
             s->complete(r, PPC_OK, 0, r.arrival, r.arrival, zeros);
         } else {
-            s->queue.push_back({r, bytes});
+            s->queue.push_back({r, bytes, slab});
+            if (r.timeout > 0) ++s->queued_with_timeout;
         }
     }
     s->note();
@@ -603,7 +622,7 @@ int ppc_server_submit(ppc_server* s, const ppc_request* reqs, uint32_t n) {
 
 int ppc_server_progress(ppc_server* s, uint32_t* launched, uint32_t* completed) {
     if (!s) return PPC_ERR_NULL;
-    const uint32_t c = s->reap();
+    const uint32_t c = s->reap() + s->expire();
     s->admit();
     const uint32_t l = s->launch();
     s->note();
@@ -628,6 +647,21 @@ int ppc_server_take_completions(ppc_server* s, ppc_completion* out, uint32_t cap
 int ppc_server_get_stats(const ppc_server* s, ppc_server_stats* out) {
     if (!s || !out) return PPC_ERR_NULL;
     *out = s->stats;
+    return PPC_OK;
+}
+
+int ppc_server_cancel(ppc_server* s, uint64_t tag, uint32_t* cancelled) {
+    if (!s) return PPC_ERR_NULL;
+    const uint32_t n = s->cancel(tag);
+    s->note();
+    if (cancelled) *cancelled = n;
+    return PPC_OK;
+}
+
+int ppc_server_arena(const ppc_server* s, void** base, uint64_t* bytes) {
+    if (!s || !base || !bytes) return PPC_ERR_NULL;
+    *base = s->arena_base;
+    *bytes = s->arena.size();
     return PPC_OK;
 }
 

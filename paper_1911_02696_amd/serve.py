@@ -15,15 +15,16 @@ from . import _lib as L
 from ._lib import check
 
 REQUEST_DTYPE = np.dtype([("src", "<u8"), ("n", "<u8"), ("k", "<u4"), ("reserved", "<u4"),
-                          ("arrival", "<f8"), ("tag", "<u8")])
+                          ("arrival", "<f8"), ("tag", "<u8"), ("timeout", "<f8")])
 COMPLETION_DTYPE = np.dtype([("tag", "<u8"), ("status", "<i4"), ("batch", "<u4"),
                              ("arrival", "<f8"), ("admitted", "<f8"), ("launched", "<f8"),
-                             ("completed", "<f8"), ("counts", "<u8", (32,))])
+                             ("completed", "<f8"), ("counts", "<u8", (32,)),
+                             ("arena_offset", "<u8")])
 EXEC_ITEM_DTYPE = np.dtype([("src", "<u8"), ("n", "<u8"), ("k", "<u4"), ("reserved", "<u4"),
                             ("arena_offset", "<u8"), ("tag", "<u8")])
 STATS_FIELDS = ("submitted", "admitted", "completed", "rejected", "launches", "queued_now",
                 "inflight_now", "max_queued", "max_inflight", "arena_used_now", "arena_peak",
-                "bytes_counted")
+                "bytes_counted", "expired", "cancelled")
 
 IN_PLACE, FIFO_BYPASS = 1, 2
 
@@ -62,10 +63,12 @@ L.register_signatures({
     "ppc_server_take_completions": (_i32, [_vp, _vp, _u32, ctypes.POINTER(_u32)]),
     "ppc_server_get_stats": (_i32, [_vp, ctypes.POINTER(ServerStats)]),
     "ppc_server_run_trace": (_i32, [_vp, _vp, _u32, _vp]),
+    "ppc_server_cancel": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(_u32)]),
+    "ppc_server_arena": (_i32, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_uint64)]),
 })
 
 
-def requests(srcs, ns, ks, arrivals=None, tags=None) -> np.ndarray:
+def requests(srcs, ns, ks, arrivals=None, tags=None, timeouts=None) -> np.ndarray:
     m = len(ns)
     r = np.zeros(m, REQUEST_DTYPE)
     r["src"] = np.asarray(srcs, dtype=np.uint64)
@@ -73,6 +76,7 @@ def requests(srcs, ns, ks, arrivals=None, tags=None) -> np.ndarray:
     r["k"] = np.asarray(ks, dtype=np.uint32)
     r["arrival"] = 0.0 if arrivals is None else np.asarray(arrivals, dtype=np.float64)
     r["tag"] = np.arange(m, dtype=np.uint64) if tags is None else np.asarray(tags, np.uint64)
+    r["timeout"] = 0.0 if timeouts is None else np.asarray(timeouts, dtype=np.float64)
     return r
 
 
@@ -131,6 +135,18 @@ class Server:
         check(L.lib().ppc_server_take_completions(self.handle, out.ctypes.data, cap,
                                                   ctypes.byref(n)))
         return out[:n.value]
+
+    def cancel(self, tag: int) -> int:
+        n = ctypes.c_uint32()
+        check(L.lib().ppc_server_cancel(self.handle, tag, ctypes.byref(n)), "ppc_server_cancel")
+        return n.value
+
+    def arena(self) -> tuple[int, int]:
+        """(device address, bytes) of the server's arena; address 0 in place."""
+        base, size = ctypes.c_void_p(), ctypes.c_uint64()
+        check(L.lib().ppc_server_arena(self.handle, ctypes.byref(base), ctypes.byref(size)),
+              "ppc_server_arena")
+        return base.value or 0, size.value
 
     def stats(self) -> dict:
         s = ServerStats()

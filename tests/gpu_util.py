@@ -41,3 +41,33 @@ def oracle_counts(host: np.ndarray, n: int, k: int, threads: int | None = None) 
 def counts_np(t: torch.Tensor) -> np.ndarray:
     torch.cuda.synchronize()
     return t.cpu().numpy().astype(np.int64)
+
+
+_HIP = None
+
+
+def hip():
+    """The HIP runtime torch has loaded (same soname as the library's), for raw
+    device memory the tests did not allocate through torch (a server's arena)."""
+    global _HIP
+    if _HIP is None:
+        import ctypes
+        torch.cuda.init()
+        h = ctypes.CDLL("libamdhip64.so.7")
+        h.hipMemset.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t]
+        h.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        h.hipDeviceSynchronize.argtypes = []
+        _HIP = h
+    return _HIP
+
+
+def device_fill(ptr: int, value: int, nbytes: int):
+    assert hip().hipMemset(ptr, value, nbytes) == 0
+    assert hip().hipDeviceSynchronize() == 0
+
+
+def device_read(ptr: int, nbytes: int) -> np.ndarray:
+    out = np.empty(nbytes, np.uint8)
+    assert hip().hipDeviceSynchronize() == 0
+    assert hip().hipMemcpy(out.ctypes.data, ptr, nbytes, 2) == 0  # device to host
+    return out

@@ -319,3 +319,94 @@ def test_server_argument_checks():
     ops = S.ExecutorOps()
     assert lib.ppc_server_create_with_executor(ctypes.byref(S.ServerConfig(1, 1, 1, 1, 0)),
                                                ctypes.byref(ops), None, ctypes.byref(h)) == 1
+
+
+def test_timeout_expires_only_waiting_requests():
+    """A request still waiting for memory when its timeout passes completes with
+    PPC_ERR_TIMEOUT and is never launched; one without a timeout waits on."""
+    import time
+    arena = 16 << 10
+    host = I.generate(64 << 10, I.Dist.uniform(), 11)
+    base = host.ctypes.data
+    reqs = S.requests([base, base + 20000, base + 40000], [12 << 10, 10 << 10, 10 << 10],
+                      [8, 8, 8], tags=[0, 1, 2], timeouts=[0.0, 0.05, 0.0])
+    ex = FakeExecutor(arena, delay=10 ** 9)  # request 0 holds the arena until released
+    srv = S.Server(arena, max_requests=10, max_batch=10, streams=1, executor=ex.ops)
+    reqs["arrival"] = srv.now()
+    srv.submit(reqs)
+    srv.progress()
+    time.sleep(0.08)
+    srv.progress()
+    first = srv.take_completions()
+    assert first["tag"].tolist() == [1] and first["status"].tolist() == [11]  # TIMEOUT
+    ex.delay = 1
+    comps = drive(srv)
+    assert sorted(comps["tag"].tolist()) == [0, 2] and (comps["status"] == 0).all()
+    assert [t for launch in ex.log for t in launch] == [0, 2]
+    st = srv.stats()
+    assert st["expired"] == 1 and st["completed"] == 3 and st["arena_used_now"] == 0
+
+
+def test_cancel_waiting_and_admitted_requests():
+    """Cancelling drops a waiting request and an admitted one that is not launched yet
+    (its slab is given back); a launched request runs to completion."""
+    w = Workload(6, 12, max_bytes=2000)
+    ex = FakeExecutor(1 << 20, delay=10 ** 9)
+    # one launch slot pair (streams=1) and one request per launch: after two steps,
+    # requests 0 and 1 are launched and 2..5 admitted but not launched
+    srv = S.Server(1 << 20, max_requests=5, max_batch=1, streams=1, executor=ex.ops)
+    srv.submit(w.reqs)
+    srv.progress()
+    srv.progress()
+    assert [t for launch in ex.log for t in launch] == [0, 1]
+    used = srv.stats()["arena_used_now"]
+    assert srv.cancel(3) == 1       # admitted, not launched
+    assert srv.stats()["arena_used_now"] < used
+    assert srv.cancel(5) == 1       # waiting (slot limit)
+    assert srv.cancel(0) == 0       # launched: not cancelled
+    assert srv.cancel(77) == 0      # unknown tag
+    c = srv.take_completions()
+    assert sorted(c["tag"].tolist()) == [3, 5] and (c["status"] == 12).all()  # CANCELLED
+    ex.delay = 1
+    comps = drive(srv)
+    assert sorted(comps["tag"].tolist()) == [0, 1, 2, 4] and (comps["status"] == 0).all()
+    for x in comps:
+        t = int(x["tag"])
+        assert (x["counts"][:w.k[t]] == w.expected(t)).all()
+    st = srv.stats()
+    assert st["cancelled"] == 2 and st["arena_used_now"] == 0 and st["completed"] == 6
+
+
+def test_timeout_argument_checks():
+    host = np.zeros(64, np.uint8)
+    r = S.requests([host.ctypes.data] * 3, [4, 4, 4], [8, 8, 8], timeouts=[-1.0, np.nan, 0.5])
+    ex = FakeExecutor(1 << 20)
+    srv = S.Server(1 << 20, executor=ex.ops)
+    srv.submit(r)
+    c = srv.take_completions()
+    assert c["status"].tolist() == [7, 7]  # negative and NaN timeouts: PPC_ERR_ARG
+    comps = drive(srv)
+    assert comps["status"].tolist() == [0]
+
+
+@pytest.mark.parametrize("in_place", [False, True])
+def test_copy_slab_holds_the_source_shift(in_place):
+    """In copy mode a request's copy starts at its source address modulo 16 inside its
+    slab, which is sized for that; in place the slab is the input size."""
+    host = I.generate(4096, I.Dist.uniform(), 13)
+    base = (host.ctypes.data + 15) & ~15
+    r = S.requests([base + 1, base + 512 + 15], [256, 240], [8, 8], tags=[0, 1])
+    ex = FakeExecutor(1 << 20, delay=10 ** 9)
+    srv = S.Server(1 << 20, max_requests=10, max_batch=10, streams=1, in_place=in_place,
+                   executor=ex.ops)
+    srv.submit(r)
+    srv.progress()
+    # 256 + 1 bytes need two granules in copy mode; 240 + 15 fit one
+    assert srv.stats()["arena_used_now"] == (768 if not in_place else 512)
+    ex.delay = 1
+    comps = drive(srv)
+    comps = comps[np.argsort(comps["tag"])]
+    items = ex.log
+    assert (comps["status"] == 0).all() and items == [[0, 1]]
+    shift = np.array([1, 15]) if not in_place else np.array([0, 0])
+    assert ((comps["arena_offset"] - shift) % 256 == 0).all()
