@@ -17,7 +17,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libppc_oracle.so")
+# PPC_ORACLE_LIB names another build of the same source (the sanitizer run uses it).
+LIB_PATH = os.environ.get("PPC_ORACLE_LIB") or os.path.join(_HERE, "libppc_oracle.so")
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 _u64p = ctypes.POINTER(ctypes.c_uint64)

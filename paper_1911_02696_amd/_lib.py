@@ -10,7 +10,8 @@ import os
 import threading
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libpospopcnt.so")
+# PPC_LIB names another build of the same sources (the sanitizer run uses it).
+LIB_PATH = os.environ.get("PPC_LIB") or os.path.join(PKG, "libpospopcnt.so")
 
 PPC_OK = 0
 STATUS_NAMES = {

@@ -24,7 +24,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libppc_gen.so")
+# PPC_GEN_LIB names another build of the same source (the sanitizer run uses it).
+LIB_PATH = os.environ.get("PPC_GEN_LIB") or os.path.join(_HERE, "libppc_gen.so")
 
 UNIFORM, BERNOULLI, ONEHOT, IDS = 0, 1, 2, 3
 
