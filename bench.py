@@ -264,6 +264,7 @@ def serving_leg(args, torch, api):
         warm = r[:2000].copy()
         warm["arrival"] = np.linspace(0, 0.02, len(warm))
         srv.run_trace(warm)
+        warm_bytes = srv.stats()["bytes_counted"]
         srv.close()
         srv = S.Server(64 << 30, max_requests=4096, max_batch=1024, streams=4,
                        in_place=(mode == "in_place"))
@@ -289,6 +290,7 @@ def serving_leg(args, torch, api):
         report[mode] = dict(lat, seconds=seconds, gbps=round(st["bytes_counted"] / span / 1e9, 1),
                             requests_per_s=round(len(r) / span, 1),
                             launches=st["launches"], admitted=st["admitted"],
+                            bytes_counted=st["bytes_counted"], warmup_bytes_counted=warm_bytes,
                             rejected=st["rejected"], max_queued=st["max_queued"],
                             max_inflight=st["max_inflight"],
                             arena_peak_gib=round(st["arena_peak"] / 2**30, 3),
@@ -421,6 +423,129 @@ def wide_leg(args, torch, api):
     return out, ok
 
 
+def calls_leg(args, torch, api):
+    """The fixed cost of one call on a small input (C1: 2^20 uint16 words, 2 MiB,
+    resident in the last-level cache): host time per call of 2000 back-to-back
+    pospopcnt16 calls through the Python binding, and the same from C through the
+    library's C ABI (the C caller in tests/c_abi, when built).  The kernel itself takes
+    a few microseconds, so both are bound by the host's launch path."""
+    import subprocess
+    n, calls = 1 << 20, 2000
+    x = torch.full((2 * n,), 0x5A, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(16, dtype=torch.int64, device="cuda")
+    for _ in range(100):
+        api.pospopcnt(x, 16, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        api.pospopcnt(x, 16, out=out)
+    torch.cuda.synchronize()
+    py_us = (time.perf_counter() - t0) / calls * 1e6
+    want = np.array([n * (calls + 100) if (0x5A5A >> q) & 1 else 0 for q in range(16)])
+    ok = bool((out.cpu().numpy() == want).all())
+    rep = {"workload": "2^20 uint16 words (2 MiB), 2000 back-to-back calls on one stream",
+           "python_us_per_call": round(py_us, 3), "python_gbps": round(2 * n / py_us / 1e3, 1)}
+    exe = os.path.join(ROOT, "tests", "c_abi", "abi_check")
+    if os.path.exists(exe):
+        res = subprocess.run([exe, "calls", str(calls)], capture_output=True, text=True)
+        c = json.loads(res.stdout.strip().splitlines()[-1]) if res.returncode == 0 else None
+        ok &= c is not None and c.get("ok", False)
+        if c:
+            rep["c_us_per_call"] = c["c_us_per_call"]
+            rep["python_over_c"] = round(py_us / c["c_us_per_call"], 2)
+    rep["check"] = ok
+    del x
+    return rep, ok
+
+
+def variants_leg(args, torch, api):
+    """The three counting kernels on the same 16 GiB of Bernoulli(0.5) bytes, read as
+    8-, 16- and 32-bit words, each at its default launch shape: the per-lane CSA circuit
+    (csa), the wave-wide ballot transposition (ballot) and the CSA circuit with its
+    carries counted by ballot (hybrid).  Timed with HIP events over args.steps launches
+    after args.warmup.  Check: every variant's counts equal the CSA kernel's."""
+    nbytes = 1 << 34
+    dev = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    upload(dev, nbytes, I.Dist.uniform(), SEED + 9)
+    stream = torch.cuda.current_stream()
+    out, ok = {"bytes": nbytes}, True
+    for k in (8, 16, 32):
+        n = nbytes // (k // 8)
+        ref = api.pospopcnt(dev, k, n=n).cpu().numpy()
+        row = {}
+        for variant in ("csa", "hybrid", "ballot"):
+            counts = torch.zeros(k, dtype=torch.int64, device="cuda")
+            for _ in range(args.warmup):
+                api.pospopcnt(dev, k, n=n, out=counts, variant=variant)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                api.pospopcnt(dev, k, n=n, out=counts, variant=variant)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 1e3 / max(args.steps, 1)
+            good = bool((counts.cpu().numpy() == ref * (args.warmup + args.steps)).all())
+            ok &= good
+            row[variant] = {"gbps": round(nbytes / t / 1e9, 1),
+                            "frac_of_hbm_peak": round(nbytes / t / 1e9 / HBM_PEAK_GBPS, 4),
+                            "check": good}
+        out[f"u{k}"] = row
+        print(f"[bench] variants k={k}: {row}", file=sys.stderr, flush=True)
+    del dev
+    torch.cuda.empty_cache()
+    return out, ok
+
+
+DEPTH_SHAPES = [(64, b) for b in (2, 3, 4, 6, 8, 12, 16)] + [(256, b) for b in (1, 2, 3, 4)]
+
+
+def depth_leg(args, torch, api):
+    """Circuit depth against throughput (Sec. 4.1 compares 256 B, 512 B and 1 kB
+    circuits): for 8-, 16- and 32-bit words over the same 16 GiB of Bernoulli(0.5)
+    bytes, every circuit depth (4, 8, 16, 32 dwords per lane per step) at every launch
+    shape of DEPTH_SHAPES (block size x blocks per CU), each timed with HIP events
+    over args.steps launches after args.warmup; reports each depth's best shape and
+    its GB/s.  Check: every configuration's counts equal the default one's."""
+    nbytes = 1 << 34
+    dev = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    upload(dev, nbytes, I.Dist.uniform(), SEED + 9)
+    stream = torch.cuda.current_stream()
+    out, ok = {"bytes": nbytes, "shapes": [list(x) for x in DEPTH_SHAPES]}, True
+    for k in (8, 16, 32):
+        n = nbytes // (k // 8)
+        ref = api.pospopcnt(dev, k, n=n).cpu().numpy()
+        per_depth = {}
+        for depth in (4, 8, 16, 32):
+            rows = []
+            for threads, bpc in DEPTH_SHAPES:
+                cfg = dict(depth=depth, block_threads=threads, blocks_per_cu=bpc)
+                counts = torch.zeros(k, dtype=torch.int64, device="cuda")
+                for _ in range(args.warmup):
+                    api.pospopcnt(dev, k, n=n, out=counts, **cfg)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(args.steps):
+                    api.pospopcnt(dev, k, n=n, out=counts, **cfg)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1) / 1e3 / args.steps
+                good = bool((counts.cpu().numpy() == ref * (args.warmup + args.steps)).all())
+                ok &= good
+                rows.append((round(nbytes / t / 1e9, 1), threads, bpc, good))
+            best = max(rows)
+            per_depth[str(depth)] = {"best_gbps": best[0], "best_block_threads": best[1],
+                                     "best_blocks_per_cu": best[2],
+                                     "frac_of_hbm_peak": round(best[0] / HBM_PEAK_GBPS, 4),
+                                     "gbps_by_shape": [r[0] for r in rows],
+                                     "check": all(r[3] for r in rows)}
+            print(f"[bench] depth k={k} d={depth}: best {best[0]} GB/s at {best[1]}x{best[2]}",
+                  file=sys.stderr, flush=True)
+        out[f"u{k}"] = per_depth
+    del dev
+    torch.cuda.empty_cache()
+    return out, ok
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -439,9 +564,11 @@ def main():
     ap.add_argument("--batched-profile", action="store_true",
                     help="batched leg for counter profiling: the tuned shape set directly, no "
                          "graph, no autotuning and no per-stream comparison")
-    ap.add_argument("--legs", default="single,batched,serving,onehot,wide",
-                    help="comma-separated subset of single,batched,serving,onehot,wide to run "
-                         "(the full JSON line is printed only when the single leg runs)")
+    ap.add_argument("--legs", default="single,batched,serving,onehot,wide,calls",
+                    help="comma-separated subset of single,batched,serving,onehot,wide,calls,"
+                         "depth,variants to run (the full JSON line is printed only when the "
+                         "single leg runs; depth, the circuit-depth sweep, and variants, the three "
+                         "counting kernels side by side, run only when named)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=50_000.0,
                     help="Poisson arrival rate of the serving leg, requests/s")
@@ -472,13 +599,19 @@ def main():
         return
 
     legs = set(args.legs.split(","))
-    if not legs <= {"single", "batched", "serving", "onehot", "wide"}:
-        ap.error("--legs takes single, batched, serving, onehot and wide")
+    if not legs <= {"single", "batched", "serving", "onehot", "wide", "calls", "depth", "variants"}:
+        ap.error("--legs takes single, batched, serving, onehot, wide, calls, depth and variants")
     args.no_batched |= "batched" not in legs
     args.no_serving |= "serving" not in legs
     if "single" not in legs:
         torch.cuda.set_device(0)
         out = {}
+        if "depth" in legs:
+            out["depth"] = depth_leg(args, torch, api)[0]
+        if "calls" in legs:
+            out["calls"] = calls_leg(args, torch, api)[0]
+        if "variants" in legs:
+            out["variants"] = variants_leg(args, torch, api)[0]
         if "onehot" in legs:
             out["onehot"] = onehot_leg(args, torch, api)[0]
         if "wide" in legs:
@@ -613,6 +746,12 @@ def main():
     wide, ok_wide = None, True
     if "wide" in legs:
         wide, ok_wide = wide_leg(args, torch, api)
+    depth, ok_depth = None, True
+    if "depth" in legs:
+        depth, ok_depth = depth_leg(args, torch, api)
+    calls, ok_calls = None, True
+    if "calls" in legs:
+        calls, ok_calls = calls_leg(args, torch, api)
 
     achieved = nbytes / avg_kernel / 1e9
     src_hash = kernel_source_hash()
@@ -658,6 +797,8 @@ def main():
         "serving": serving,
         "histogram": onehot,
         "wide": wide,
+        "depth": depth,
+        "calls": calls,
         "cpu_baseline": cpu,
         "check": {"total_equals_passes_times_one_pass": ok_total,
                   "sample_equals_oracle": ok_sample},
@@ -666,7 +807,7 @@ def main():
     }
     print(json.dumps(line), flush=True)
     if not ok_total or ok_sample is False or not ok_batched or not ok_serving or not ok_onehot \
-            or not ok_wide:
+            or not ok_wide or not ok_depth or not ok_calls:
         sys.exit(1)
 
 

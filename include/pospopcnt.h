@@ -100,9 +100,10 @@ enum {
 typedef struct {
     int32_t variant;        /* PPC_VARIANT_CSA, or PPC_VARIANT_BALLOT or _HYBRID (k <= 32
                                only) */
-    int32_t depth;          /* CSA, HYBRID: inputs per lane per circuit, 8, 16 or 32 dwords
-                               (the 2^N-input circuits of Sec. 2; the paper's 256 B /
-                               512 B / 1 kB circuits are N = 2, 3, 4) */
+    int32_t depth;          /* CSA, HYBRID: inputs per lane per circuit, 4, 8, 16 or 32
+                               dwords (the 2^N-input circuits of Sec. 2, N = 2 .. 5; the
+                               paper's 256 B / 512 B / 1 kB circuits have the same
+                               input counts as N = 2, 3, 4: 3 / 7 / 15 CSAs per step) */
     int32_t block_threads;  /* 64 .. 256, multiple of 64 */
     int32_t blocks_per_cu;  /* resident blocks per compute unit used to size the grid */
     int64_t grid;           /* explicit number of blocks (overrides blocks_per_cu) */
@@ -197,7 +198,7 @@ typedef struct {
  * units), the stream_weight standing for the fixed cost of its edge bytes and
  * its flush.  Block b of the grid takes exactly the b-th share. */
 typedef struct {
-    int32_t depth;          /* circuit inputs per lane per step: 16 or 32 dwords */
+    int32_t depth;          /* circuit inputs per lane per step: 4, 8, 16 or 32 dwords */
     int32_t block_threads;  /* 64, 128 or 256 */
     int32_t blocks_per_cu;  /* 1 .. 16; grid = blocks_per_cu * compute units */
     int32_t stream_weight;  /* weighted units charged per stream, 1 .. 65536 */
@@ -241,9 +242,10 @@ int pospopcnt_batch(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, ppc_str
 /* Times candidate configurations on the given workload (counts are redirected
  * to plan scratch, so the descriptors' counters are not touched), keeps the
  * fastest in the plan and returns its time per call in *best_ms (may be NULL).
- * Every candidate (56 shapes of depth, block size, blocks per CU and stream
- * weight) is timed 3 times; the 4 with the lowest medians are then timed 5
- * times more, in turn, and the lowest median of those decides.  Synchronises
+ * Every candidate (144 shapes: depth 4, 8, 16 or 32, and per depth 28 shapes of
+ * one-wave blocks, 1 .. 16 per CU, times four stream weights, and 8 of
+ * four-wave blocks) is timed 3 times; the 4 with the lowest medians are then
+ * timed 5 times more, in turn, and the lowest median of those decides.  Synchronises
  * `stream`; on an error the plan keeps its previous configuration. */
 int ppc_plan_autotune(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, ppc_stream stream,
                       float* best_ms);

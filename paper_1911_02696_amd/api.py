@@ -24,7 +24,7 @@ VARIANTS = {"csa": L.VARIANT_CSA, "ballot": L.VARIANT_BALLOT, "hybrid": L.VARIAN
 def stream_handle(stream=None) -> int:
     """A hipStream_t as an int: torch's current stream when stream is None."""
     if stream is None:
-        return torch.cuda.current_stream().cuda_stream
+        return torch._C._cuda_getCurrentRawStream(torch.cuda.current_device())
     if isinstance(stream, torch.cuda.Stream):
         return stream.cuda_stream
     return int(stream)
@@ -36,9 +36,10 @@ def _launch_on(stream, fresh) -> int:
     supplied the output): a launch on another stream first waits for that fill,
     and the tensor is marked as used by that stream, so that its memory is not
     handed out again before the launch ends."""
-    cur = torch.cuda.current_stream()
     if stream is None:
-        return cur.cuda_stream
+        # torch's current stream as a raw handle, without building a Stream object
+        return torch._C._cuda_getCurrentRawStream(torch.cuda.current_device())
+    cur = torch.cuda.current_stream()
     if isinstance(stream, torch.cuda.Stream):
         if fresh is not None and stream != cur:
             stream.wait_stream(cur)
@@ -82,8 +83,9 @@ def _counts_tensor(out, k, device):
 def pospopcnt_ptr(ptr: int, n: int, k: int, counts_ptr: int, stream=None, config=None) -> None:
     """Raw call: counts_ptr[p] += count of bit p over n k-bit words at device address ptr."""
     cfg = ctypes.byref(config) if config is not None else None
-    check(L.lib().pospopcnt_ex(ptr or None, n, k, counts_ptr or None, stream_handle(stream), cfg),
-          f"pospopcnt(k={k}, n={n})")
+    st = L.lib().pospopcnt_ex(ptr or None, n, k, counts_ptr or None, stream_handle(stream), cfg)
+    if st:
+        raise PpcError(st, f"pospopcnt(k={k}, n={n})")
 
 
 def pospopcnt(x: torch.Tensor, k: int, n: int | None = None, byte_offset: int = 0,
@@ -104,6 +106,10 @@ def pospopcnt(x: torch.Tensor, k: int, n: int | None = None, byte_offset: int = 
     fresh = out is None
     out = _counts_tensor(out, k, x.device)
     cfg = launch_config(**config) if config else None
+    if x.device.index == torch.cuda.current_device():  # no device switch needed
+        s = _launch_on(stream, out if fresh else None)
+        pospopcnt_ptr(x.data_ptr() + byte_offset, n, k, out.data_ptr(), s, cfg)
+        return out
     with torch.cuda.device(x.device):
         s = _launch_on(stream, out if fresh else None)
         pospopcnt_ptr(x.data_ptr() + byte_offset, n, k, out.data_ptr(), s, cfg)

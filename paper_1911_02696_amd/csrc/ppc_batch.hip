@@ -507,9 +507,7 @@ batch_main(const ppc_desc* __restrict__ descs, uint8_t* const* __restrict__ dsts
 }
 
 // Circuit depths 4, 8, 16 and 32 dwords per lane (LOGD 2 .. 5).
-static int logd_of(int depth) {
-    return depth == 4 ? 2 : depth == 8 ? 3 : depth == 16 ? 4 : depth == 32 ? 5 : -1;
-}
+static int logd_of(int depth) { return logd_of_depth(depth); }
 
 static const void* main_kernel(int depth, bool copy) {
     static const void* const plain[4] = {(const void*)batch_main<2, false>,
@@ -908,13 +906,15 @@ int ppc_plan_autotune(ppc_plan* pl, const ppc_desc* d_descs, uint32_t m, ppc_str
     int st = device_of(pl);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
+    // Shallow circuits keep fewer bytes in flight per wave (4 dwords per lane per
+    // tile at depth 4), so the axis of waves per CU reaches 16.
     std::vector<ppc_batch_config> cands;
-    for (int depth : {16, 32})
-        for (int bpc : {2, 3, 4, 6, 8, 12})
+    for (int depth : {4, 8, 16, 32}) {
+        for (int bpc : {2, 3, 4, 6, 8, 12, 16})
             for (int weight : {1024, 2048, 4096, 8192}) cands.push_back({depth, 64, bpc, weight});
-    for (int depth : {16, 32})
-        for (int bpc : {1, 2})
+        for (int bpc : {1, 2, 3, 4})
             for (int weight : {2048, 4096}) cands.push_back({depth, 256, bpc, weight});
+    }
     hipEvent_t e0, e1;
     PPC_HIP(hipEventCreate(&e0));
     hipError_t he = hipEventCreate(&e1);

@@ -330,6 +330,42 @@ __device__ __forceinline__ uint32_t edge_dword_copy(const Edges& e, int lane, in
     return (uint32_t)byte << (8u * (uint32_t)((uintptr_t)p & 3u));
 }
 
+// As walk_n with P tiles in flight (P >= 2): P - 1 tiles are loaded ahead of the
+// one being consumed.  The steady-state body handles P tiles with the buffer
+// indices fixed at compile time; the last tiles (fewer than 2P - 1) are handled by
+// an unrolled tail whose conditions are uniform over the wave.
+template <int U, int P, typename F>
+__device__ __forceinline__ void walk_np(const u32x4* __restrict__ p, uint64_t count,
+                                        uint64_t stride, F&& consume) {
+    static_assert(P >= 2, "at least two tiles in flight");
+    if constexpr (P == 2) {
+        walk_n<U>(p, count, stride, consume);
+    } else {
+        if (count == 0) return;
+        u32x4 buf[P][U];
+#pragma unroll
+        for (int j = 0; j < P - 1; ++j)
+            if ((uint64_t)j < count) load_tile<U>(buf[j], p + j * stride);
+        while (count >= 2 * P - 1) {
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                load_tile<U>(buf[(j + P - 1) % P], p + (j + P - 1) * stride);
+                consume_tile<U>(consume, buf[j], p + j * stride);
+            }
+            p += P * stride;
+            count -= P;
+        }
+#pragma unroll
+        for (int j = 0; j < 2 * P - 2; ++j) {
+            if ((uint64_t)j < count) {
+                if ((uint64_t)(j + P - 1) < count)
+                    load_tile<U>(buf[(j + P - 1) % P], p + (j + P - 1) * stride);
+                consume_tile<U>(consume, buf[j % P], p + j * stride);
+            }
+        }
+    }
+}
+
 // Walk this wave's whole tiles t = gw, gw + nw, ... < full of a body.
 template <int U, typename F>
 __device__ __forceinline__ void walk_tiles(const u32x4* __restrict__ body, uint64_t full,
@@ -337,6 +373,15 @@ __device__ __forceinline__ void walk_tiles(const u32x4* __restrict__ body, uint6
     constexpr uint64_t TILE = (uint64_t)kWave * U;
     if (gw >= full) return;
     walk_n<U>(body + gw * TILE + lane, (full - gw + nw - 1) / nw, nw * TILE, consume);
+}
+
+// As walk_tiles with P tiles in flight per wave.
+template <int U, int P, typename F>
+__device__ __forceinline__ void walk_tiles_p(const u32x4* __restrict__ body, uint64_t full,
+                                             uint64_t gw, uint64_t nw, int lane, F&& consume) {
+    constexpr uint64_t TILE = (uint64_t)kWave * U;
+    if (gw >= full) return;
+    walk_np<U, P>(body + gw * TILE + lane, (full - gw + nw - 1) / nw, nw * TILE, consume);
 }
 
 template <int C, int LOGD, int U>

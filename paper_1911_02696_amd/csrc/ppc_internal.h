@@ -89,4 +89,9 @@ constexpr uint64_t kDirectReads = 2048;
 int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has_edges,
                    uint64_t nbytes, Launch* out);
 
+// log2 of a circuit depth of 4, 8, 16 or 32 dwords per lane; -1 for any other.
+inline int logd_of_depth(int depth) {
+    return depth == 4 ? 2 : depth == 8 ? 3 : depth == 16 ? 4 : depth == 32 ? 5 : -1;
+}
+
 }  // namespace ppc

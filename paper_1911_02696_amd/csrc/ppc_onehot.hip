@@ -246,6 +246,11 @@ __device__ __forceinline__ uint32_t edge_onehot(const Edges& e, int lane, uint32
     return id < (uint32_t)C ? 1u << id : 0u;
 }
 
+// Tiles in flight per wave while one is turned into codes and counted.
+constexpr int onehot_inflight(int code_bits, int id_bytes) {
+    return (void)code_bits, (void)id_bytes, 2;
+}
+
 // bins <= C categories counted with C-bit codes: classes bins .. C-1 hold ids that
 // have a code but no category, and are flushed into counts[bins] with the rest.
 template <int C, int IDB>
@@ -272,7 +277,7 @@ onehot_kernel(const u32x4* __restrict__ body, uint64_t units, Edges edges, uint3
     TileTree<C, LOGD, E> tree;
     tree.init();
     const bool all[U] = {true, true, true, true};
-    walk_tiles<U>(body, full, gw, nw, lane, [&](const u32x4(&v)[U]) {
+    walk_tiles_p<U, onehot_inflight(C, IDB)>(body, full, gw, nw, lane, [&](const u32x4(&v)[U]) {
         tree.add(onehot_step<C, IDB, LOGD>(B, ph, v, all, false));
     });
     // ids this lane has seen: 4 / IDB per input dword, 16 dwords per tile

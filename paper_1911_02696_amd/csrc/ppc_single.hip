@@ -188,18 +188,23 @@ using CeilKernel = void (*)(const u32x4*, uint64_t, Edges, unsigned long long*);
 
 static int class_index(int k) { return k == 8 ? 0 : k == 16 ? 1 : 2; }
 
-static StreamKernel csa_table[3][3] = {
-    {csa_kernel<8, 3>, csa_kernel<8, 4>, csa_kernel<8, 5>},
-    {csa_kernel<16, 3>, csa_kernel<16, 4>, csa_kernel<16, 5>},
-    {csa_kernel<32, 3>, csa_kernel<32, 4>, csa_kernel<32, 5>},
+// Circuits of 4, 8, 16 and 32 dwords per lane per step (LOGD 2 .. 5): the GPU
+// counterparts of the 256 B, 512 B and 1 kB circuits of Sec. 4.1 (3, 7 and 15
+// CSAs per step), plus one of 32 inputs.
+constexpr int kMinLogd = 2;
+static StreamKernel csa_table[3][4] = {
+    {csa_kernel<8, 2>, csa_kernel<8, 3>, csa_kernel<8, 4>, csa_kernel<8, 5>},
+    {csa_kernel<16, 2>, csa_kernel<16, 3>, csa_kernel<16, 4>, csa_kernel<16, 5>},
+    {csa_kernel<32, 2>, csa_kernel<32, 3>, csa_kernel<32, 4>, csa_kernel<32, 5>},
 };
 static StreamKernel ballot_table[3] = {ballot_kernel<8>, ballot_kernel<16>, ballot_kernel<32>};
-static StreamKernel hybrid_table[3][3] = {
-    {hybrid_kernel<8, 3>, hybrid_kernel<8, 4>, hybrid_kernel<8, 5>},
-    {hybrid_kernel<16, 3>, hybrid_kernel<16, 4>, hybrid_kernel<16, 5>},
-    {hybrid_kernel<32, 3>, hybrid_kernel<32, 4>, hybrid_kernel<32, 5>},
+static StreamKernel hybrid_table[3][4] = {
+    {hybrid_kernel<8, 2>, hybrid_kernel<8, 3>, hybrid_kernel<8, 4>, hybrid_kernel<8, 5>},
+    {hybrid_kernel<16, 2>, hybrid_kernel<16, 3>, hybrid_kernel<16, 4>, hybrid_kernel<16, 5>},
+    {hybrid_kernel<32, 2>, hybrid_kernel<32, 3>, hybrid_kernel<32, 4>, hybrid_kernel<32, 5>},
 };
-static CeilKernel ceil_table[3] = {ceiling_kernel<3>, ceiling_kernel<4>, ceiling_kernel<5>};
+static CeilKernel ceil_table[4] = {ceiling_kernel<2>, ceiling_kernel<3>, ceiling_kernel<4>,
+                                   ceiling_kernel<5>};
 
 // Default launch shape per width and size, measured on MI355X over 256 MiB - 16 GiB
 // inputs: a circuit of 16 dwords per lane per step (as many inputs as the paper's
@@ -245,8 +250,9 @@ static int occupancy(const void* kernel, int threads) {
 
 static const void* kernel_of(int variant, int k, int logd) {
     if (variant == PPC_VARIANT_BALLOT) return (const void*)ballot_table[class_index(k)];
-    if (variant == PPC_VARIANT_HYBRID) return (const void*)hybrid_table[class_index(k)][logd - 3];
-    return (const void*)csa_table[class_index(k)][logd - 3];
+    if (variant == PPC_VARIANT_HYBRID)
+        return (const void*)hybrid_table[class_index(k)][logd - kMinLogd];
+    return (const void*)csa_table[class_index(k)][logd - kMinLogd];
 }
 
 int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has_edges,
@@ -258,10 +264,8 @@ int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has
         return PPC_ERR_ARG;
     int logd = default_logd(k);
     if (c.depth) {
-        if (c.depth == 8) logd = 3;
-        else if (c.depth == 16) logd = 4;
-        else if (c.depth == 32) logd = 5;
-        else return PPC_ERR_ARG;
+        logd = logd_of_depth(c.depth);
+        if (logd < 0) return PPC_ERR_ARG;
     }
     const Shape shape = c.variant == PPC_VARIANT_HYBRID ? hybrid_shape() : default_shape(k, nbytes);
     const int threads = c.block_threads ? c.block_threads : shape.threads;
@@ -370,7 +374,7 @@ int ppc_read_ceiling(const void* ptr, uint64_t nbytes, uint64_t* sink, ppc_strea
     uint64_t units = s.units;
     unsigned long long* sp = (unsigned long long*)sink;
     void* args[] = {&body, &units, &e, &sp};
-    PPC_HIP(hipLaunchKernel((const void*)ceil_table[L.logd - 3], dim3((uint32_t)L.grid),
+    PPC_HIP(hipLaunchKernel((const void*)ceil_table[L.logd - kMinLogd], dim3((uint32_t)L.grid),
                             dim3(L.threads), args, 0, (hipStream_t)stream));
     return PPC_OK;
 }

@@ -123,15 +123,19 @@ planes16_kernel(PlaneTable t) {
 using Wide64Kernel = void (*)(const u32x4*, uint64_t, Edges, uint32_t, unsigned long long*);
 using PlanesKernel = void (*)(PlaneTable);
 
-// Circuit inputs per lane and tile, both parities: 8, 16 (default) or 32 dwords.
+// Circuit inputs per lane and tile, both parities: 4, 8, 16 (default) or 32 dwords;
+// the cross-tile levels make every depth count classes once per 64 dwords of a
+// parity.
 static const void* wide64_of(int depth) {
-    static Wide64Kernel table[3] = {wide64_kernel<2, 4>, wide64_kernel<3, 3>, wide64_kernel<4, 2>};
-    return (const void*)table[depth == 8 ? 0 : depth == 16 ? 1 : 2];
+    static Wide64Kernel table[4] = {wide64_kernel<1, 5>, wide64_kernel<2, 4>, wide64_kernel<3, 3>,
+                                    wide64_kernel<4, 2>};
+    return (const void*)table[logd_of_depth(depth) - 2];
 }
 
 static const void* planes_of(int depth) {
-    static PlanesKernel table[3] = {planes16_kernel<3>, planes16_kernel<4>, planes16_kernel<5>};
-    return (const void*)table[depth == 8 ? 0 : depth == 16 ? 1 : 2];
+    static PlanesKernel table[4] = {planes16_kernel<2>, planes16_kernel<3>, planes16_kernel<4>,
+                                    planes16_kernel<5>};
+    return (const void*)table[logd_of_depth(depth) - 2];
 }
 
 // Shared launch-shape rules: the configuration's block size and blocks per CU,
@@ -145,7 +149,7 @@ static int wide_shape(const ppc_launch_config* cfg, int def_threads, int def_bpc
     if (cfg) c = *cfg;
     if (c.variant != PPC_VARIANT_CSA) return PPC_ERR_ARG;
     const int depth = c.depth ? c.depth : 16;
-    if (depth != 8 && depth != 16 && depth != 32) return PPC_ERR_ARG;
+    if (logd_of_depth(depth) < 0) return PPC_ERR_ARG;
     const int threads = c.block_threads ? c.block_threads : def_threads;
     if (threads < kWave || threads > kWideThreads || threads % kWave) return PPC_ERR_ARG;
     if (c.blocks_per_cu < 0 || c.grid < 0) return PPC_ERR_ARG;

@@ -6,11 +6,17 @@
  *   abi_check gpu   counts of device buffers against closed forms: all-ones words
  *                   set every position once per word, all-zero words none, and a
  *                   constant id stream falls in that id's category (or outside)
+ *   abi_check calls N   host time per call of N back-to-back pospopcnt_u16 calls on
+ *                   2^20 words (2 MiB) on the null stream, after 100 untimed calls;
+ *                   prints {"c_us_per_call": ...} (the per-call cost of the boundary
+ *                   itself, with no Python in between)
  *
  * Prints one line and exits 0 when every check holds, 1 otherwise. */
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #include <hip/hip_runtime_api.h>
 
@@ -48,7 +54,8 @@ static int cpu_checks(void) {
     EXPECT(ppc_histogram_u8(NULL, 10, 8, fake_counts, NULL) == PPC_ERR_NULL);
     EXPECT(ppc_histogram_u8((const void*)0x1000, 10, 33, fake_counts, NULL) == PPC_ERR_WIDTH);
     EXPECT(ppc_histogram_u8((const void*)0x1000, 10, 0, fake_counts, NULL) == PPC_ERR_WIDTH);
-    for (int st = 0; st <= 10; ++st) {
+    EXPECT(PPC_ERR_TIMEOUT == 11 && PPC_ERR_CANCELLED == 12);
+    for (int st = 0; st <= 12; ++st) {
         const char* s = ppc_status_string(st);
         EXPECT(s != NULL && strlen(s) > 0);
     }
@@ -115,9 +122,44 @@ static int gpu_checks(void) {
     return failures;
 }
 
+static double now_s(void) {
+    struct timespec t;
+    clock_gettime(CLOCK_MONOTONIC, &t);
+    return (double)t.tv_sec + 1e-9 * (double)t.tv_nsec;
+}
+
+static int time_calls(long calls) {
+    const uint64_t n = 1u << 20;
+    void* buf = NULL;
+    uint64_t* d_counts = NULL;
+    if (calls < 1 || hipMalloc(&buf, 2 * n) != hipSuccess ||
+        hipMalloc((void**)&d_counts, 8 * 16) != hipSuccess) {
+        fprintf(stderr, "bad call count or hipMalloc failed\n");
+        return 1;
+    }
+    EXPECT(hipMemset(buf, 0x5A, 2 * n) == hipSuccess && hipMemset(d_counts, 0, 128) == hipSuccess);
+    for (int i = 0; i < 100; ++i) EXPECT(pospopcnt_u16(buf, n, d_counts, NULL) == PPC_OK);
+    EXPECT(hipDeviceSynchronize() == hipSuccess);
+    const double t0 = now_s();
+    for (long i = 0; i < calls; ++i)
+        if (pospopcnt_u16(buf, n, d_counts, NULL) != PPC_OK) ++failures;
+    EXPECT(hipDeviceSynchronize() == hipSuccess);
+    const double dt = now_s() - t0;
+    uint64_t h[16];
+    EXPECT(read_counts(d_counts, h, 16));
+    /* 0x5A5A = bits 1, 3, 4, 6 of each byte set: positions 1,3,4,6,9,11,12,14 */
+    for (int q = 0; q < 16; ++q)
+        EXPECT(h[q] == (((0x5A5Au >> q) & 1u) ? n * (uint64_t)(calls + 100) : 0));
+    EXPECT(hipFree(buf) == hipSuccess && hipFree(d_counts) == hipSuccess);
+    printf("{\"c_us_per_call\": %.3f, \"calls\": %ld, \"words\": %llu, \"ok\": %s}\n",
+           1e6 * dt / (double)calls, calls, (unsigned long long)n, failures ? "false" : "true");
+    return failures ? 1 : 0;
+}
+
 int main(int argc, char** argv) {
+    if (argc == 3 && strcmp(argv[1], "calls") == 0) return time_calls(atol(argv[2]));
     if (argc != 2 || (strcmp(argv[1], "cpu") != 0 && strcmp(argv[1], "gpu") != 0)) {
-        fprintf(stderr, "usage: %s cpu|gpu\n", argv[0]);
+        fprintf(stderr, "usage: %s cpu|gpu|calls N\n", argv[0]);
         return 2;
     }
     const int gpu = strcmp(argv[1], "gpu") == 0;

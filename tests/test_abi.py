@@ -146,6 +146,7 @@ def test_length_overflow(lib):
 
 def test_bad_launch_config(lib):
     bad = [L.LaunchConfig(variant=7), L.LaunchConfig(depth=12), L.LaunchConfig(depth=64),
+           L.LaunchConfig(depth=2), L.LaunchConfig(depth=-4),
            L.LaunchConfig(block_threads=96), L.LaunchConfig(block_threads=512),
            L.LaunchConfig(block_threads=32), L.LaunchConfig(blocks_per_cu=-1),
            L.LaunchConfig(grid=-5)]

@@ -79,6 +79,10 @@ def test_batch_matches_oracle(small_batch):
 
 
 @pytest.mark.parametrize("cfg", [
+    dict(depth=4, block_threads=64, blocks_per_cu=16, stream_weight=2048),
+    dict(depth=4, block_threads=256, blocks_per_cu=2, stream_weight=3),
+    dict(depth=8, block_threads=64, blocks_per_cu=6, stream_weight=4096),
+    dict(depth=8, block_threads=128, blocks_per_cu=1, stream_weight=1),
     dict(depth=16, block_threads=64, blocks_per_cu=1, stream_weight=1),
     dict(depth=16, block_threads=256, blocks_per_cu=16, stream_weight=65536),
     dict(depth=32, block_threads=128, blocks_per_cu=3, stream_weight=17),
@@ -92,6 +96,25 @@ def test_batch_configs_agree(small_batch, cfg):
     plan.config = cfg
     assert plan.config == cfg
     say(f"batch config {cfg}")
+    plan.run(b.descs)
+    torch.cuda.synchronize()
+    b.check()
+
+
+@pytest.mark.parametrize("depth", [4, 8, 16, 32])
+def test_long_stream_pieces_drain_the_vertical_counter(depth):
+    """A wave's piece of a long stream is walked in chunks of 254 tiles, the carry
+    counter drained after each: three streams of 64-384 MiB over one-wave blocks,
+    one per CU, give each wave 2.5 MiB, more than 254 tiles at every depth (a tile
+    is 64 lanes x depth dwords, 8 KiB at depth 32), next to short streams."""
+    lengths = np.array([(384 << 20) + 5, 3, (192 << 20) // 2 + 1, 17, (64 << 20) // 4 - 3],
+                       dtype=np.uint64)
+    ks = np.array([8, 16, 16, 32, 32], dtype=np.int32)
+    s = I.StreamSet(lengths, ks, np.array([0.5, 0.5, 0.1, 0.9, 0.7]))
+    b = Batch(s, SEED + 60 + depth, threads=I.default_threads())
+    plan = B.Plan(b.m)
+    plan.config = dict(depth=depth, block_threads=64, blocks_per_cu=1, stream_weight=1)
+    say(f"batch long pieces depth {depth}")
     plan.run(b.descs)
     torch.cuda.synchronize()
     b.check()

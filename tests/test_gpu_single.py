@@ -45,8 +45,10 @@ def test_lengths_and_offsets(k):
 
 @pytest.mark.parametrize("k", KS)
 @pytest.mark.parametrize("cfg", [
-    dict(variant="csa", depth=8), dict(variant="csa", depth=16), dict(variant="csa", depth=32),
-    dict(variant="ballot"), dict(variant="hybrid", depth=8), dict(variant="hybrid", depth=16),
+    dict(variant="csa", depth=4), dict(variant="csa", depth=8), dict(variant="csa", depth=16),
+    dict(variant="csa", depth=32), dict(variant="csa", depth=4, block_threads=64, grid=5),
+    dict(variant="ballot"), dict(variant="hybrid", depth=4), dict(variant="hybrid", depth=8),
+    dict(variant="hybrid", depth=16),
     dict(variant="hybrid", depth=32, block_threads=64), dict(block_threads=64),
     dict(block_threads=128),
     dict(grid=1), dict(grid=7), dict(blocks_per_cu=1), dict(depth=32, grid=3, block_threads=64),

@@ -35,8 +35,9 @@ def test_k64_lengths_and_offsets():
 
 
 @pytest.mark.parametrize("cfg", [
-    dict(depth=8), dict(depth=16), dict(depth=32), dict(block_threads=64),
+    dict(depth=4), dict(depth=8), dict(depth=16), dict(depth=32), dict(block_threads=64),
     dict(block_threads=128), dict(grid=1), dict(grid=7), dict(blocks_per_cu=3),
+    dict(depth=4, grid=3, block_threads=64),
     dict(depth=32, grid=3, block_threads=64),
 ], ids=lambda c: "-".join(f"{a}{b}" for a, b in c.items()))
 def test_k64_launch_configs_agree(cfg):
@@ -128,7 +129,8 @@ def test_planes_equal_interleaved_words():
     assert (got == oracle_counts(host, n, 64)).all()
 
 
-@pytest.mark.parametrize("cfg", [dict(depth=8), dict(depth=32), dict(block_threads=64),
+@pytest.mark.parametrize("cfg", [dict(depth=4), dict(depth=8), dict(depth=32),
+                                 dict(block_threads=64),
                                  dict(grid=1), dict(grid=5), dict(blocks_per_cu=4)],
                          ids=lambda c: "-".join(f"{a}{b}" for a, b in c.items()))
 def test_planes_launch_configs_agree(cfg):
