@@ -111,7 +111,13 @@ typedef struct {
 
 /* pospopcnt with an explicit launch configuration (NULL = defaults).  Same
  * contract and errors as pospopcnt, plus PPC_ERR_ARG for a field out of range.
- * Every configuration gives the same counts. */
+ * Every configuration gives the same counts.
+ * Overrides: the environment variable PPC_LAUNCH_U8, _U16, _U32 or _U64 (per
+ * width), else PPC_LAUNCH, read once per process, as "key=value,..." with keys
+ * variant (csa, ballot, hybrid), depth, block_threads, blocks_per_cu and grid,
+ * fills the fields a call leaves at zero, for pospopcnt_ex and for every
+ * single-stream call without a configuration.  A variable that does not parse
+ * makes every such call with n > 0 return PPC_ERR_ARG. */
 int pospopcnt_ex(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stream stream,
                  const ppc_launch_config* config);
 
@@ -219,8 +225,11 @@ typedef struct ppc_plan ppc_plan;
  * 2048 streams for the split preparation, a per-block start table and an
  * autotuning sink of 256 bytes per block of the largest grid, 1 MiB on 256
  * compute units) and a default configuration.  This is the only batched call
- * that allocates.  Errors: PPC_ERR_NULL, PPC_ERR_ARG (max_streams = 0 or
- * > 2^26), PPC_ERR_HIP. */
+ * that allocates.  The environment variable PPC_BATCH_CONFIG
+ * ("depth=16,block_threads=64,blocks_per_cu=4,stream_weight=2048", any subset of
+ * the keys) overrides the default configuration of every new plan.
+ * Errors: PPC_ERR_NULL, PPC_ERR_ARG (max_streams = 0 or > 2^26, or a
+ * PPC_BATCH_CONFIG that does not parse or is out of range), PPC_ERR_HIP. */
 int ppc_plan_create(const ppc_workload_hint* hint, ppc_plan** plan);
 
 /* Releases the plan's scratch and graphs, after waiting for the plan's device to
@@ -260,6 +269,20 @@ int ppc_plan_set_config(ppc_plan* plan, const ppc_batch_config* config);
  * PPC_ERR_ARG if it cannot be parsed; the plan is then unchanged. */
 int ppc_plan_save(const ppc_plan* plan, const char* path);
 int ppc_plan_load(ppc_plan* plan, const char* path);
+
+/* A file of tuned configurations keyed by workload, for reuse across runs: the key
+ * is (device architecture, compute units, floor(log2 m), floor(log2 bytes)), where m
+ * is the number of streams and bytes their total input size.  The file holds one
+ * JSON object per line.
+ * ppc_plan_cache_put stores the plan's configuration under the key of (m, bytes),
+ * replacing an entry with the same key; the file is rewritten through path.tmp and
+ * a rename.  ppc_plan_cache_get sets the plan's configuration from the entry with
+ * that key.  Errors: PPC_ERR_NULL, PPC_ERR_ARG (m or bytes 0, a file that cannot be
+ * written, or a line that does not parse), and for get PPC_ERR_STATE when there is
+ * no entry for the key (a missing file is an empty cache); the plan is then
+ * unchanged.  Neither call touches the device. */
+int ppc_plan_cache_put(const ppc_plan* plan, const char* path, uint32_t m, uint64_t bytes);
+int ppc_plan_cache_get(ppc_plan* plan, const char* path, uint32_t m, uint64_t bytes);
 
 /* Number of descriptors the last completed pospopcnt_batch call on this plan
  * skipped as invalid.  Enqueues a 4-byte copy on stream and waits for it. */

@@ -86,6 +86,8 @@ SIGNATURES = {
     "ppc_plan_set_config": (_i32, [_vp, ctypes.POINTER(BatchConfig)]),
     "ppc_plan_save": (_i32, [_vp, ctypes.c_char_p]),
     "ppc_plan_load": (_i32, [_vp, ctypes.c_char_p]),
+    "ppc_plan_cache_put": (_i32, [_vp, ctypes.c_char_p, ctypes.c_uint32, ctypes.c_uint64]),
+    "ppc_plan_cache_get": (_i32, [_vp, ctypes.c_char_p, ctypes.c_uint32, ctypes.c_uint64]),
     "ppc_plan_rejected": (_i32, [_vp, _vp, ctypes.POINTER(_u32)]),
     "pospopcnt_each": (_i32, [_vp, _u32, _vp]),
     "pospopcnt_batch_static": (_i32, [_vp, _u32, ctypes.POINTER(BatchConfig), _vp]),

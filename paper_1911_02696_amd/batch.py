@@ -117,6 +117,19 @@ class Plan:
     def load(self, path: str):
         check(L.lib().ppc_plan_load(self.handle, path.encode()), "ppc_plan_load")
 
+    def cache_put(self, path: str, m: int, nbytes: int):
+        """Store the configuration in a cache file under the key of (m streams, nbytes)."""
+        check(L.lib().ppc_plan_cache_put(self.handle, path.encode(), m, nbytes),
+              "ppc_plan_cache_put")
+
+    def cache_get(self, path: str, m: int, nbytes: int) -> bool:
+        """Take the configuration stored for (m, nbytes); False if the cache has none."""
+        st = L.lib().ppc_plan_cache_get(self.handle, path.encode(), m, nbytes)
+        if st == 9:  # PPC_ERR_STATE: no entry for this key
+            return False
+        check(st, "ppc_plan_cache_get")
+        return True
+
     def rejected(self, stream=None) -> int:
         out = ctypes.c_uint32()
         check(L.lib().ppc_plan_rejected(self.handle, stream_handle(stream), ctypes.byref(out)))

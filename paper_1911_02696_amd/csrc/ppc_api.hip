@@ -1,4 +1,5 @@
 // ppc_api.hip -- status codes, argument checks, stream splitting, device facts.
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -35,6 +36,91 @@ int current_device(const DeviceFacts** out) {
     }
     *out = &f;
     return PPC_OK;
+}
+
+bool parse_kv(const char* text, int (*apply)(void*, const char*, const char*), void* ctx) {
+    char buf[512];
+    if (!text || strlen(text) >= sizeof(buf)) return false;
+    strcpy(buf, text);
+    char* save = nullptr;
+    for (char* tok = strtok_r(buf, ",", &save); tok; tok = strtok_r(nullptr, ",", &save)) {
+        while (*tok == ' ') ++tok;
+        char* eq = strchr(tok, '=');
+        if (!eq || eq == tok || !eq[1]) return false;
+        *eq = 0;
+        if (!apply(ctx, tok, eq + 1)) return false;
+    }
+    return true;
+}
+
+static bool to_int(const char* v, long long* out) {
+    char* end = nullptr;
+    const long long x = strtoll(v, &end, 10);
+    if (!end || end == v || *end) return false;
+    *out = x;
+    return true;
+}
+
+static int apply_launch(void* ctx, const char* key, const char* value) {
+    ppc_launch_config& c = *(ppc_launch_config*)ctx;
+    long long x = 0;
+    if (!strcmp(key, "variant")) {
+        if (!strcmp(value, "csa")) c.variant = PPC_VARIANT_CSA;
+        else if (!strcmp(value, "ballot")) c.variant = PPC_VARIANT_BALLOT;
+        else if (!strcmp(value, "hybrid")) c.variant = PPC_VARIANT_HYBRID;
+        else if (to_int(value, &x) && x >= 0 && x <= 2) c.variant = (int32_t)x;
+        else return 0;
+        return 1;
+    }
+    if (!to_int(value, &x) || x < 0 || x > 0x7fffffff) return 0;
+    if (!strcmp(key, "depth")) c.depth = (int32_t)x;
+    else if (!strcmp(key, "block_threads")) c.block_threads = (int32_t)x;
+    else if (!strcmp(key, "blocks_per_cu")) c.blocks_per_cu = (int32_t)x;
+    else if (!strcmp(key, "grid")) c.grid = x;
+    else return 0;
+    return 1;
+}
+
+const EnvLaunch& env_launch(int k) {
+    static EnvLaunch table[4];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char* names[4] = {"PPC_LAUNCH_U8", "PPC_LAUNCH_U16", "PPC_LAUNCH_U32",
+                                "PPC_LAUNCH_U64"};
+        const char* all = getenv("PPC_LAUNCH");
+        for (int i = 0; i < 4; ++i) {
+            const char* v = getenv(names[i]);
+            if (!v) v = all;
+            if (!v) continue;
+            table[i].set = true;
+            table[i].bad = !parse_kv(v, apply_launch, &table[i].cfg);
+        }
+    });
+    return table[k == 8 ? 0 : k == 16 ? 1 : k == 32 ? 2 : 3];
+}
+
+static int apply_batch(void* ctx, const char* key, const char* value) {
+    ppc_batch_config& c = *(ppc_batch_config*)ctx;
+    long long x = 0;
+    if (!to_int(value, &x) || x < 0 || x > 0x7fffffff) return 0;
+    if (!strcmp(key, "depth")) c.depth = (int32_t)x;
+    else if (!strcmp(key, "block_threads")) c.block_threads = (int32_t)x;
+    else if (!strcmp(key, "blocks_per_cu")) c.blocks_per_cu = (int32_t)x;
+    else if (!strcmp(key, "stream_weight")) c.stream_weight = (int32_t)x;
+    else return 0;
+    return 1;
+}
+
+const EnvBatch& env_batch() {
+    static EnvBatch e;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char* v = getenv("PPC_BATCH_CONFIG");
+        if (!v) return;
+        e.set = true;
+        e.bad = !parse_kv(v, apply_batch, &e.cfg);
+    });
+    return e;
 }
 
 Split split_stream(const void* ptr, uint64_t nbytes, int k) {

@@ -39,6 +39,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -765,6 +766,16 @@ int ppc_plan_create(const ppc_workload_hint* hint, ppc_plan** out) {
     if (!hint || !out) return PPC_ERR_NULL;
     *out = nullptr;
     if (hint->max_streams == 0 || hint->max_streams > kMaxPlanStreams) return PPC_ERR_ARG;
+    // the configuration a new plan starts from: the default, or the environment's
+    ppc_batch_config initial = default_config();
+    const EnvBatch& env = env_batch();
+    if (env.set) {
+        if (env.cfg.depth) initial.depth = env.cfg.depth;
+        if (env.cfg.block_threads) initial.block_threads = env.cfg.block_threads;
+        if (env.cfg.blocks_per_cu) initial.blocks_per_cu = env.cfg.blocks_per_cu;
+        if (env.cfg.stream_weight) initial.stream_weight = env.cfg.stream_weight;
+        if (env.bad || check_config(initial)) return PPC_ERR_ARG;
+    }
     const DeviceFacts* dev = nullptr;
     int st = current_device(&dev);
     if (st) return st;
@@ -775,7 +786,7 @@ int ppc_plan_create(const ppc_workload_hint* hint, ppc_plan** out) {
     pl->cus = dev->cus;
     pl->gmax = dev->cus * kMaxBlocksPerCu;
     memcpy(pl->arch, dev->arch, sizeof(pl->arch));
-    pl->cfg = default_config();
+    pl->cfg = initial;
     const size_t cum_bytes = ((size_t)hint->max_streams + 1) * 8;
     const size_t first_bytes = (size_t)pl->gmax * 4;
     const size_t off_first = (cum_bytes + 255) & ~(size_t)255;
@@ -1026,6 +1037,109 @@ int ppc_plan_load(ppc_plan* pl, const char* path) {
     pl->cfg = c;
     ++pl->cfg_version;
     return PPC_OK;
+}
+
+// ---- keyed cache of tuned configurations: one JSON object per line
+
+static int floor_log2(uint64_t x) {
+    int r = -1;
+    while (x) {
+        x >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+struct CacheKey {
+    char arch[64];
+    int cus, streams_log2, bytes_log2;
+};
+
+static bool parse_entry(const char* line, CacheKey* key, ppc_batch_config* c) {
+    const char* a = strstr(line, "\"arch\"");
+    if (!a || sscanf(a, "\"arch\": \"%63[^\"]\"", key->arch) != 1) return false;
+    return json_int(line, "cus", &key->cus) && json_int(line, "streams_log2", &key->streams_log2) &&
+           json_int(line, "bytes_log2", &key->bytes_log2) && json_int(line, "depth", &c->depth) &&
+           json_int(line, "block_threads", &c->block_threads) &&
+           json_int(line, "blocks_per_cu", &c->blocks_per_cu) &&
+           json_int(line, "stream_weight", &c->stream_weight);
+}
+
+static bool same_key(const CacheKey& a, const CacheKey& b) {
+    return !strcmp(a.arch, b.arch) && a.cus == b.cus && a.streams_log2 == b.streams_log2 &&
+           a.bytes_log2 == b.bytes_log2;
+}
+
+static CacheKey key_of(const ppc_plan* pl, uint32_t m, uint64_t bytes) {
+    CacheKey k;
+    memset(&k, 0, sizeof(k));
+    memcpy(k.arch, pl->arch, sizeof(k.arch));
+    k.arch[sizeof(k.arch) - 1] = 0;
+    k.cus = pl->cus;
+    k.streams_log2 = floor_log2(m);
+    k.bytes_log2 = floor_log2(bytes);
+    return k;
+}
+
+// Reads every line of a cache file; a missing file is an empty cache.  false if a
+// line does not parse.
+static bool read_cache(const char* path, std::vector<std::pair<CacheKey, ppc_batch_config>>* out) {
+    FILE* f = fopen(path, "r");
+    if (!f) return true;
+    char line[1024];
+    bool ok = true;
+    while (fgets(line, sizeof(line), f)) {
+        if (line[0] == '\n' || line[0] == 0) continue;
+        CacheKey k;
+        ppc_batch_config c{};
+        if (!parse_entry(line, &k, &c)) {
+            ok = false;
+            break;
+        }
+        out->push_back({k, c});
+    }
+    fclose(f);
+    return ok;
+}
+
+int ppc_plan_cache_put(const ppc_plan* pl, const char* path, uint32_t m, uint64_t bytes) {
+    if (!pl || !path) return PPC_ERR_NULL;
+    if (m == 0 || bytes == 0) return PPC_ERR_ARG;
+    std::vector<std::pair<CacheKey, ppc_batch_config>> entries;
+    if (!read_cache(path, &entries)) return PPC_ERR_ARG;
+    const CacheKey key = key_of(pl, m, bytes);
+    std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return PPC_ERR_ARG;
+    auto write = [&](const CacheKey& k, const ppc_batch_config& c) {
+        fprintf(f,
+                "{\"arch\": \"%s\", \"cus\": %d, \"streams_log2\": %d, \"bytes_log2\": %d, "
+                "\"depth\": %d, \"block_threads\": %d, \"blocks_per_cu\": %d, "
+                "\"stream_weight\": %d}\n",
+                k.arch, k.cus, k.streams_log2, k.bytes_log2, c.depth, c.block_threads,
+                c.blocks_per_cu, c.stream_weight);
+    };
+    for (const auto& e : entries)
+        if (!same_key(e.first, key)) write(e.first, e.second);
+    write(key, pl->cfg);
+    if (fclose(f) != 0) return PPC_ERR_ARG;
+    return rename(tmp.c_str(), path) == 0 ? PPC_OK : PPC_ERR_ARG;
+}
+
+int ppc_plan_cache_get(ppc_plan* pl, const char* path, uint32_t m, uint64_t bytes) {
+    if (!pl || !path) return PPC_ERR_NULL;
+    if (m == 0 || bytes == 0) return PPC_ERR_ARG;
+    std::vector<std::pair<CacheKey, ppc_batch_config>> entries;
+    if (!read_cache(path, &entries)) return PPC_ERR_ARG;
+    const CacheKey key = key_of(pl, m, bytes);
+    for (auto it = entries.rbegin(); it != entries.rend(); ++it) {
+        if (!same_key(it->first, key)) continue;
+        if (check_config(it->second)) return PPC_ERR_ARG;
+        pl->cfg = it->second;
+        ++pl->cfg_version;
+        return PPC_OK;
+    }
+    return PPC_ERR_STATE;
 }
 
 int ppc_plan_rejected(ppc_plan* pl, ppc_stream stream, uint32_t* out) {

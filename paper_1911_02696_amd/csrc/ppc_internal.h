@@ -89,6 +89,27 @@ constexpr uint64_t kDirectReads = 2048;
 int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has_edges,
                    uint64_t nbytes, Launch* out);
 
+// Launch-shape overrides from the environment, read once per process.
+//   PPC_LAUNCH_U8 / _U16 / _U32 / _U64, else PPC_LAUNCH: "key=value,..." with keys
+//   variant (csa, ballot, hybrid or 0..2), depth, block_threads, blocks_per_cu and
+//   grid.  They fill the fields a call leaves at zero (an explicit configuration
+//   wins).  *bad is set when the variable does not parse.
+struct EnvLaunch {
+    ppc_launch_config cfg{};
+    bool set = false, bad = false;
+};
+const EnvLaunch& env_launch(int k);
+// PPC_BATCH_CONFIG: "depth=..,block_threads=..,blocks_per_cu=..,stream_weight=..", the
+// initial configuration of every new plan (absent fields keep the default).
+struct EnvBatch {
+    ppc_batch_config cfg{};
+    bool set = false, bad = false;
+};
+const EnvBatch& env_batch();
+// Parses "key=value,key=value" into (key, value) pairs; false on a syntax error.
+bool parse_kv(const char* text, int (*apply)(void* ctx, const char* key, const char* value),
+              void* ctx);
+
 // log2 of a circuit depth of 4, 8, 16 or 32 dwords per lane; -1 for any other.
 inline int logd_of_depth(int depth) {
     return depth == 4 ? 2 : depth == 8 ? 3 : depth == 16 ? 4 : depth == 32 ? 5 : -1;

@@ -311,8 +311,27 @@ int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has
     return PPC_OK;
 }
 
+// The call's configuration with the environment's overrides in its zero fields.
+static int merged_config(int k, const ppc_launch_config* cfg, ppc_launch_config* out) {
+    *out = cfg ? *cfg : ppc_launch_config{};
+    const EnvLaunch& e = env_launch(k);
+    if (!e.set) return PPC_OK;
+    if (e.bad) return PPC_ERR_ARG;
+    if (!out->variant) out->variant = e.cfg.variant;
+    if (!out->depth) out->depth = e.cfg.depth;
+    if (!out->block_threads) out->block_threads = e.cfg.block_threads;
+    if (!out->blocks_per_cu) out->blocks_per_cu = e.cfg.blocks_per_cu;
+    if (!out->grid) out->grid = e.cfg.grid;
+    return PPC_OK;
+}
+
 int launch_stream(const void* ptr, uint64_t n, int k, uint64_t* counts, ppc_stream stream,
-                  const ppc_launch_config* cfg) {
+                  const ppc_launch_config* cfg_in) {
+    if (k != 8 && k != 16 && k != 32 && k != 64) return PPC_ERR_WIDTH;
+    if (n == 0) return PPC_OK;
+    ppc_launch_config merged;
+    if (int mst = merged_config(k, cfg_in, &merged)) return mst;
+    const ppc_launch_config* cfg = &merged;
     if (k == 64) return launch_wide64(ptr, n, counts, stream, cfg);
     uint64_t nbytes = 0;
     int st = check_stream_args(ptr, n, k, counts, &nbytes);

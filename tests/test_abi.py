@@ -284,3 +284,58 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "all raised" in r.stdout
+
+
+def _in_fresh_process(env_extra: dict, code: str) -> str:
+    """Runs `code` in a new Python (the overrides are read once per process)."""
+    env = dict(os.environ, **env_extra)
+    res = subprocess.run(["python", "-c", "import sys; sys.path.insert(0, %r)\n" % ROOT + code],
+                         env=env, capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0, res.stderr
+    return res.stdout.strip()
+
+
+CALL = """
+import ctypes
+from paper_1911_02696_amd import _lib as L
+lib = L.lib()
+cfg = L.LaunchConfig(0, 16, 0, 0, 0)
+print(lib.pospopcnt(0x1000, 64, 16, 0x80000, None), lib.pospopcnt_u8(0x1000, 64, 0x80000, None),
+      lib.pospopcnt_ex(0x1000, 64, 16, 0x80000, None, ctypes.byref(cfg)),
+      lib.pospopcnt(0x1000, 0, 16, 0x80000, None))
+"""
+
+
+@pytest.mark.parametrize("env,expect", [
+    # a variable that does not parse: every launching call fails with PPC_ERR_ARG
+    ({"PPC_LAUNCH": "depth16"}, "7 7 7 0"),
+    ({"PPC_LAUNCH": "depth=16,colour=red"}, "7 7 7 0"),
+    # parses, but out of range: the fields it fills fail validation; an explicit
+    # depth replaces the bad one and the call gets as far as the device (no GPU here)
+    ({"PPC_LAUNCH": "depth=12"}, "7 7 5 0"),
+    # a per-width variable wins over the general one
+    ({"PPC_LAUNCH": "depth=12", "PPC_LAUNCH_U16": "depth=8"}, "5 7 5 0"),
+    ({"PPC_LAUNCH_U8": "variant=hybrid,block_threads=96"}, "5 7 5 0"),
+    ({"PPC_LAUNCH": "variant=ballot,depth=32,block_threads=256,blocks_per_cu=2,grid=0"},
+     "5 5 5 0"),
+])
+def test_launch_overrides_from_the_environment(env, expect):
+    assert _in_fresh_process(env, CALL) == expect
+
+
+PLAN = """
+import ctypes
+from paper_1911_02696_amd import _lib as L
+h = ctypes.c_void_p()
+hint = L.WorkloadHint(16, 0)
+print(L.lib().ppc_plan_create(ctypes.byref(hint), ctypes.byref(h)))
+"""
+
+
+@pytest.mark.parametrize("value,expect", [
+    ("depth=12", "7"), ("blocks_per_cu=17", "7"), ("stream_weight", "7"), ("threads=64", "7"),
+    # valid: plan creation then needs the device, which this machine lacks
+    ("depth=4,block_threads=256,blocks_per_cu=2,stream_weight=100", "5"),
+])
+def test_batch_config_override_is_checked_before_the_device(value, expect):
+    assert _in_fresh_process({"PPC_BATCH_CONFIG": value}, PLAN) == expect

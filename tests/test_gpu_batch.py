@@ -302,3 +302,37 @@ def test_many_streams_short_axis_and_one_long_stream():
     plan.run(bt.descs)
     torch.cuda.synchronize()
     bt.check(which=[17, 2500, 4999, 0, 4998])
+
+
+def test_plan_cache_round_trip(tmp_path, small_batch):
+    """Tuned configurations stored per workload key (streams and bytes, log2 buckets) and
+    taken back by a new plan; a key with no entry leaves the plan as it was."""
+    b = small_batch
+    path = str(tmp_path / "plans.jsonl")
+    total = int(b.streams.nbytes.sum())
+    plan = B.Plan(b.m)
+    assert not plan.cache_get(path, b.m, total)  # no file yet: an empty cache
+    plan.config = dict(depth=8, block_threads=128, blocks_per_cu=5, stream_weight=777)
+    plan.cache_put(path, b.m, total)
+    plan.config = dict(depth=32, block_threads=64, blocks_per_cu=2, stream_weight=9)
+    plan.cache_put(path, 20_000, 13 << 30)  # another key in the same file
+    plan.config = dict(depth=4, block_threads=256, blocks_per_cu=3, stream_weight=5)
+    plan.cache_put(path, b.m + 1, total + 1)  # same buckets: replaces the first entry
+    assert len(open(path).read().splitlines()) == 2
+    fresh = B.Plan(b.m)
+    before = fresh.config
+    assert not fresh.cache_get(path, b.m, total * 4)  # another bytes bucket
+    assert fresh.config == before
+    assert fresh.cache_get(path, b.m, total)
+    assert fresh.config == dict(depth=4, block_threads=256, blocks_per_cu=3, stream_weight=5)
+    assert fresh.cache_get(path, 20_000, 13 << 30)
+    assert fresh.config["stream_weight"] == 9
+    b.counts.zero_()
+    say("batch with a cached configuration")
+    fresh.run(b.descs)
+    torch.cuda.synchronize()
+    b.check()
+    with open(path, "a") as f:
+        f.write("not json\n")
+    with pytest.raises(Exception):
+        fresh.cache_get(path, b.m, total)
