@@ -370,8 +370,9 @@ typedef struct {
 typedef struct {
     uint64_t tag;
     int32_t status;     /* PPC_OK, PPC_ERR_BUDGET (larger than the arena), PPC_ERR_WIDTH,
-                           PPC_ERR_NULL, PPC_ERR_ARG, PPC_ERR_TIMEOUT, PPC_ERR_CANCELLED,
-                           or PPC_ERR_HIP if its launch failed */
+                           PPC_ERR_NULL, PPC_ERR_ARG, PPC_ERR_OVERLAP (the input lies in
+                           the server's arena), PPC_ERR_TIMEOUT, PPC_ERR_CANCELLED, or
+                           PPC_ERR_HIP if its launch failed */
     uint32_t batch;     /* requests in the launch that counted it */
     double arrival, admitted, launched, completed;  /* server clock, seconds */
     uint64_t counts[32];                            /* first k entries used */

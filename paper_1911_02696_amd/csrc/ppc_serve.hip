@@ -381,6 +381,15 @@ struct ppc_server {
 
     bool copies() const { return (cfg.flags & PPC_SERVE_IN_PLACE) == 0; }
 
+    // A source that overlaps the arena could be overwritten by another request's copy
+    // while it is read.
+    bool inside_arena(const void* src, uint64_t bytes) const {
+        if (!arena_base || !bytes) return false;
+        const uintptr_t a0 = (uintptr_t)arena_base, a1 = a0 + arena.size();
+        const uintptr_t s0 = (uintptr_t)src, s1 = s0 + bytes;
+        return s1 < s0 || (s0 < a1 && a0 < s1);
+    }
+
     // Slab of a request: its bytes, plus in copy mode the shift of its copy.
     uint64_t slab_of(const ppc_request& r, uint64_t bytes) const {
         return bytes + (copies() ? copy_shift(r.src) : 0);
@@ -599,6 +608,7 @@ int ppc_server_submit(ppc_server* s, const ppc_request* reqs, uint32_t n) {
         else if (!(r.timeout >= 0.0)) st = PPC_ERR_ARG;  // negative or NaN
         else if (r.n > UINT64_MAX / (r.k / 8)) st = PPC_ERR_ARG;
         else if (r.n && !r.src) st = PPC_ERR_NULL;
+        else if (s->inside_arena(r.src, r.n * (r.k / 8))) st = PPC_ERR_OVERLAP;
         else {
             bytes = r.n * (r.k / 8);
             slab = bytes <= s->arena.size() ? s->slab_of(r, bytes) : 0;

@@ -123,3 +123,20 @@ def test_failed_launch_is_reported_and_serving_goes_on(monkeypatch, in_place):
         i, k = int(c["tag"]), int(case.k[c["tag"]])
         exp = oracle_counts(case.src(i), int(case.n[i]), k)
         assert (c["counts"][:k].astype(np.int64) == exp).all(), f"request {i}"
+
+
+def test_source_inside_the_arena_is_refused():
+    """A request whose input lies in the server's own arena (where other requests' copies
+    are written) completes at once with PPC_ERR_OVERLAP; the others are served."""
+    case = Case(20, 4096, SEED + 9)
+    srv = S.Server(1 << 20, max_requests=64, max_batch=64, streams=1)
+    ptr, size = srv.arena()
+    bad = S.requests([ptr + 100, ptr + size - 8, ptr - 8], [64, 64, 16], [8, 8, 8],
+                     tags=[1000, 1001, 1002])
+    srv.submit(bad)
+    first = srv.take_completions()
+    assert sorted(first["tag"].tolist()) == [1000, 1001, 1002]
+    assert (first["status"] == 8).all(), first["status"]
+    comps = drive(srv, case.reqs)
+    srv.close()
+    assert (comps["status"] == 0).all()
