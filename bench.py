@@ -584,6 +584,10 @@ def main():
               "one-GPU path is implemented).", file=sys.stderr)
         sys.exit(2)
 
+    legs = set(args.legs.split(","))
+    if not legs <= {"single", "batched", "serving", "onehot", "wide", "calls", "depth", "variants"}:
+        ap.error("--legs takes single, batched, serving, onehot, wide, calls, depth and variants")
+
     import torch
     from paper_1911_02696_amd import api
 
@@ -598,9 +602,6 @@ def main():
                           "write_bytes_per_copy": args.copy_reference}))
         return
 
-    legs = set(args.legs.split(","))
-    if not legs <= {"single", "batched", "serving", "onehot", "wide", "calls", "depth", "variants"}:
-        ap.error("--legs takes single, batched, serving, onehot, wide, calls, depth and variants")
     args.no_batched |= "batched" not in legs
     args.no_serving |= "serving" not in legs
     if "single" not in legs:

@@ -53,3 +53,11 @@ def test_kernel_source_hash_is_stable():
     h = bench.kernel_source_hash()
     assert len(h) == 16 and int(h, 16) >= 0
     assert h == bench.kernel_source_hash()
+
+
+def test_unknown_leg_is_refused_before_any_gpu_work():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--legs", "single,nope"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "--legs takes" in r.stderr
+    assert r.stdout == ""
