@@ -18,6 +18,7 @@
 // count, which in copy mode also stores every byte it reads into the request's
 // slab, so that each input byte is read once and written once; the copy of the
 // counts to pinned host memory, and an event the scheduler polls.
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
