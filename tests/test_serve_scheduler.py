@@ -410,3 +410,68 @@ def test_copy_slab_holds_the_source_shift(in_place):
     assert (comps["status"] == 0).all() and items == [[0, 1]]
     shift = np.array([1, 15]) if not in_place else np.array([0, 0])
     assert ((comps["arena_offset"] - shift) % 256 == 0).all()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_randomized_schedules_keep_the_invariants(seed):
+    """Random arrivals, sizes, slot and memory limits, launch delays, failed launches,
+    timeouts and cancellations: every request completes exactly once, with its own counts
+    or the status of what happened to it; slabs stay inside the arena and never overlap;
+    without bypass, launches follow arrival order; the arena drains."""
+    import time
+    rng = np.random.Generator(np.random.PCG64(100 + seed))
+    m = 120
+    w = Workload(m, 200 + seed, max_bytes=int(rng.integers(500, 20_000)))
+    arena = int(rng.integers(24 << 10, 256 << 10))
+    fail = set(rng.choice(40, size=int(rng.integers(0, 4)), replace=False).tolist())
+    ex = FakeExecutor(arena, delay=int(rng.integers(1, 6)), fail_launches=fail)
+    bypass = bool(rng.integers(0, 2))
+    srv = S.Server(arena, max_requests=int(rng.integers(2, 40)), max_batch=int(rng.integers(1, 12)),
+                   streams=int(rng.integers(1, 4)), fifo_bypass=bypass, executor=ex.ops)
+    reqs = w.reqs.copy()
+    timed = rng.random(m) < 0.2
+    reqs["timeout"] = np.where(timed, 1e-4, 0.0)
+    cancel_at = {int(i): int(rng.integers(0, 30)) for i in rng.choice(m, size=10, replace=False)}
+    done = []
+    step, nxt = 0, 0
+    reqs["arrival"] = 0.0
+    while len(done) < m and step < 20_000:
+        burst = int(rng.integers(0, 6))
+        if nxt < m and burst:
+            batch = reqs[nxt:nxt + burst].copy()
+            batch["arrival"] = srv.now()
+            srv.submit(batch)
+            nxt += len(batch)
+        for tag, when in list(cancel_at.items()):
+            if when == step:
+                srv.cancel(tag)
+                del cancel_at[tag]
+        if rng.random() < 0.05:
+            time.sleep(2e-4)  # lets the short timeouts pass now and then
+        srv.progress()
+        done.extend(srv.take_completions())
+        step += 1
+    comps = np.array(done, dtype=S.COMPLETION_DTYPE)
+    assert not ex.errors, ex.errors
+    assert sorted(comps["tag"].tolist()) == list(range(m)), "each request completes once"
+    failed_tags = {t for i, launch in enumerate(ex.log) if i in fail for t in launch}
+    for c in comps:
+        t = int(c["tag"])
+        st = int(c["status"])
+        if st == 0:
+            k = int(w.k[t])
+            assert (c["counts"][:k] == w.expected(t)).all(), f"request {t}"
+        elif st == 5:
+            assert t in failed_tags
+        elif st == 11:
+            assert timed[t]
+        else:
+            assert st == 12, (t, st)  # cancelled
+    launched = [t for launch in ex.log for t in launch]
+    assert len(launched) == len(set(launched))
+    if not bypass:
+        assert launched == sorted(launched), "FIFO admission keeps arrival order"
+    st = srv.stats()
+    assert st["arena_used_now"] == 0 and st["inflight_now"] == 0 and st["queued_now"] == 0
+    assert st["arena_peak"] <= arena
+    assert st["completed"] == m and st["submitted"] == m
