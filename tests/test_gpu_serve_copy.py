@@ -98,15 +98,18 @@ def test_copies_and_counts_are_exact(max_batch, m, max_bytes, arena):
     srv.close()
 
 
-@pytest.mark.parametrize("in_place", [False, True], ids=["copy", "in_place"])
-def test_failed_launch_is_reported_and_serving_goes_on(monkeypatch, in_place):
+@pytest.mark.parametrize("in_place,big", [(False, False), (True, False), (False, True)],
+                         ids=["copy", "in_place", "copy_large_launches"])
+def test_failed_launch_is_reported_and_serving_goes_on(monkeypatch, in_place, big):
     """The executor's third launch fails after its count was enqueued (fault hook):
     its requests complete with PPC_ERR_HIP, its slabs and slots drain, and every
     later request -- including those of later launches on the same counters, which
-    the failure path must have cleared -- equals the oracle."""
-    case = Case(300, 1 << 16, SEED + 7)
+    the failure path must have cleared -- equals the oracle.  With large launches
+    (more than 1024 requests) the count runs as a preparation and a main kernel."""
+    case = Case(5000, 512, SEED + 8) if big else Case(300, 1 << 16, SEED + 7)
     monkeypatch.setenv("PPC_FAULT_LAUNCH", "3")
-    srv = S.Server(1 << 20, max_requests=64, max_batch=8, streams=1, in_place=in_place)
+    srv = S.Server(1 << 22 if big else 1 << 20, max_requests=2048 if big else 64,
+                   max_batch=1100 if big else 8, streams=1, in_place=in_place)
     monkeypatch.delenv("PPC_FAULT_LAUNCH")
     say(f"serve fault hook: launch 3 of {len(case.reqs)} requests fails, in_place={in_place}")
     comps = drive(srv, case.reqs)
@@ -116,7 +119,9 @@ def test_failed_launch_is_reported_and_serving_goes_on(monkeypatch, in_place):
     assert len(failed) > 0 and (failed["status"] == 5).all(), np.unique(comps["status"])
     assert len(np.unique(failed["launched"])) == 1 and len(failed) == int(failed["batch"][0])
     assert st["arena_used_now"] == 0 and st["inflight_now"] == 0 and st["queued_now"] == 0
-    assert st["launches"] > 6
+    assert st["launches"] > (3 if big else 6)
+    if big:
+        assert failed["batch"][0] > 1024
     later = comps[(comps["status"] == 0) & (comps["launched"] > failed["launched"][0])]
     assert len(later) > 0
     for c in comps[comps["status"] == 0]:
