@@ -87,7 +87,8 @@ def test_many_small_requests_one_stream(workload):
 
 
 def test_unaligned_sources_are_copied_exactly(workload):
-    """Request inputs starting at every misalignment 0..15 (the byte-wise copy path)."""
+    """Request inputs starting at every misalignment 0..15: each copy starts at its source's
+    address modulo 16 inside its slab, counted while it is copied."""
     trace, pools, reqs = workload
     pick = np.nonzero(trace.nbytes < (1 << 20))[0][:64]
     r = reqs[pick].copy()
