@@ -16,8 +16,9 @@
 // (and, in copy mode, of where each request's copy goes), unless the launch is
 // small enough for its kernel to read them from pinned host memory; the batched
 // count, which in copy mode also stores every byte it reads into the request's
-// slab, so that each input byte is read once and written once; the copy of the
-// counts to pinned host memory, and an event the scheduler polls.
+// slab, so that each input byte is read once and written once; a small kernel that
+// moves the counts to pinned host memory and clears them for the slot's next
+// launch; and an event the scheduler polls.
 #include <stdlib.h>
 #include <string.h>
 
@@ -141,6 +142,20 @@ class CallbackExecutor : public Executor {
     size_t cap_;
 };
 
+// After a launch's count: its rows of counters go to the pinned results buffer, and the
+// counters are cleared for the slot's next launch.  One small kernel in place of a copy
+// and a fill: one launch call instead of two on the host.  It runs after the count
+// kernel on the same stream, so every flush of the count is visible to it.
+__global__ void __launch_bounds__(256) collect_counts(unsigned long long* __restrict__ dev,
+                                                      unsigned long long* __restrict__ host,
+                                                      uint32_t words) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += gridDim.x * blockDim.x) {
+        host[i] = dev[i];
+        dev[i] = 0;
+    }
+}
+
 class HipExecutor : public Executor {
   public:
     // One launch's buffers.  The descriptors and, in copy mode, the destination of
@@ -200,7 +215,9 @@ class HipExecutor : public Executor {
             // slot: fine-grained (coherent) memory, so that the device never holds a
             // stale copy of it.
             PPC_HIP(hipHostMalloc(&s.h_meta, meta, hipHostMallocCoherent));
-            PPC_HIP(hipHostMalloc(&s.h_counts, 256ull * c.max_batch));
+            // written by collect_counts: fine-grained, so that the host sees the kernel's
+            // stores once the launch's event has completed
+            PPC_HIP(hipHostMalloc(&s.h_counts, 256ull * c.max_batch, hipHostMallocCoherent));
             PPC_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
         }
         return PPC_OK;
@@ -291,12 +308,17 @@ class HipExecutor : public Executor {
         const int bst = batch_zeroed(plans_[s.stream], (const ppc_desc*)meta, n, st, bytes, dsts);
         if (bst) return abandon(bst);
         if (++launches_ == fault_launch_) return abandon(fail_hip(hipErrorLaunchFailure));
-        PPC_HIP_QUEUED(
-            hipMemcpyAsync(s.h_counts, s.d_counts, 256ull * n, hipMemcpyDeviceToHost, st));
+        // the counts to the pinned buffer, the counters cleared for the slot's next launch
+        {
+            unsigned long long* dev = (unsigned long long*)s.d_counts;
+            unsigned long long* host = (unsigned long long*)s.h_counts;
+            uint32_t words = 32u * n;
+            const uint32_t grid = std::min<uint32_t>((words + 255) / 256, 64);
+            void* cargs[] = {(void*)&dev, (void*)&host, &words};
+            PPC_HIP_QUEUED(
+                hipLaunchKernel((const void*)collect_counts, dim3(grid), dim3(256), cargs, 0, st));
+        }
         PPC_HIP_QUEUED(hipEventRecord(s.done, st));
-        // Clear the counters used, for the slot's next launch on this same stream;
-        // enqueued after the event, so the results do not wait for it.
-        PPC_HIP_QUEUED(hipMemsetAsync(s.d_counts, 0, 256ull * n, st));
 #undef PPC_HIP_QUEUED
         s.busy = true;
         s.n = n;
