@@ -418,9 +418,9 @@ typedef struct ppc_server ppc_server;
  * allocates).  Errors: PPC_ERR_NULL, PPC_ERR_ARG, PPC_ERR_HIP.
  * Fault injection for tests: with the environment variable PPC_FAULT_LAUNCH=N
  * set when the server is created, its N-th launch (counted from 1) fails with
- * PPC_ERR_HIP after its count was enqueued, as a failed copy of its results
- * would; the launch's requests complete with that status and the server goes
- * on serving. */
+ * PPC_ERR_HIP after its count was enqueued, as a failure to enqueue the
+ * collection of its results would; the launch's requests complete with that
+ * status and the server goes on serving. */
 int ppc_server_create(const ppc_server_config* config, ppc_server** server);
 
 /* Same scheduler over caller-supplied executor callbacks (no device memory is

@@ -183,7 +183,7 @@ class HipExecutor : public Executor {
         cus_ = dev->cus;
         in_place_ = (c.flags & PPC_SERVE_IN_PLACE) != 0;
         // Test hook: PPC_FAULT_LAUNCH=N makes the N-th launch (counted from 1) fail
-        // as if its results copy had failed, after its count was enqueued.
+        // after its count was enqueued, as if the collection of its results had failed.
         if (const char* f = getenv("PPC_FAULT_LAUNCH")) fault_launch_ = strtoull(f, nullptr, 10);
         if (!in_place_ && c.arena_bytes) PPC_HIP(hipMalloc(&arena_, c.arena_bytes));
         streams_.resize(c.streams, nullptr);
