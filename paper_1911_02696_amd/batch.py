@@ -146,7 +146,7 @@ def batch_static(descs: torch.Tensor, m: int | None = None, config: dict | None 
     Plan._keep(descs, stream)
     cfg = None
     if config is not None:
-        c = dict(depth=16, block_threads=64, blocks_per_cu=4, stream_weight=4096)
+        c = dict(depth=16, block_threads=64, blocks_per_cu=4, stream_weight=2048)
         c.update(config)
         cfg = ctypes.byref(BatchConfig(c["depth"], c["block_threads"], c["blocks_per_cu"],
                                        c["stream_weight"]))

@@ -692,12 +692,13 @@ static int static_scratch(int dev, char** out) {
     return PPC_OK;
 }
 
-// Measured on MI355X over a 20,000-stream uneven mix, in the given, ascending and
-// descending length orders (ppc_plan_autotune picks per workload): 16 dwords per
-// lane per step, one-wave blocks, 4 per CU, and a stream costed like 64 KiB of
-// body -- the latency of a stream's bookkeeping, first loads and flush is about
-// what a block streams in that time.
-static ppc_batch_config default_config() { return ppc_batch_config{16, 64, 4, 4096}; }
+// The autotuner's choice on MI355X for a 20,000-stream uneven mix, in every run
+// (ppc_plan_autotune picks per workload): 16 dwords per lane per step, one-wave
+// blocks, 4 per CU, and a stream costed like 32 KiB of body -- about what a block
+// streams while a stream's bookkeeping, first loads and flush take.  Against a
+// stream costed like 64 KiB the same mix ran 1.5-2% faster (6983-7018 against
+// 6852-6886 GB/s, libraries compared in one process on four machines).
+static ppc_batch_config default_config() { return ppc_batch_config{16, 64, 4, 2048}; }
 
 static int device_of(ppc_plan* pl) {
     int dev = -1;
