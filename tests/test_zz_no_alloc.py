@@ -7,6 +7,7 @@ import pytest
 import torch
 
 from paper_1911_02696_amd import _lib as L
+from paper_1911_02696_amd import api
 from paper_1911_02696_amd import batch as B
 from paper_1911_02696_amd import inputs as I
 
@@ -64,6 +65,32 @@ def test_static_equals_plan_on_calls_in_a_row():
             exp = 0 if i in bad else oracle_counts(host[st:st + n * k // 8], n, k)
             assert (got[i, :k] == exp).all(), f"call {j} stream {i}"
             assert (got[i, k:] == 0).all()
+
+
+def test_static_at_its_capacity():
+    """PPC_STATIC_MAX_STREAMS streams (the largest table the array holds) on the
+    largest grid it allows, 16 one-wave blocks per compute unit (4096 blocks on 256
+    units), against the plan-based call and a sample of the oracle."""
+    m = L.STATIC_MAX_STREAMS
+    bpc = max(1, min(16, 4096 // api.device_info()["compute_units"]))
+    cfg = dict(depth=16, block_threads=64, blocks_per_cu=bpc, stream_weight=256)
+    s, starts, host, dev, ((c_static, d_static), (c_plan, d_plan)) = \
+        _workload(m, 9, SEED + 7)
+    say(f"no-alloc batch at capacity: m={m}, config={cfg}")
+    B.batch_static(d_static, config=cfg)
+    plan = B.Plan(m)
+    plan.config = cfg
+    plan.run(d_plan)
+    torch.cuda.synchronize()
+    plan.close()
+    got, ref = c_static.cpu().numpy(), c_plan.cpu().numpy()
+    assert (got == ref).all(), "the static form differs from the plan's at capacity"
+    bad = set(range(5, m, 701))
+    for i in sorted(set(range(0, m, 97)) | {m - 1} | bad):
+        k, n, st = int(s.ks[i]), int(s.lengths[i]), int(starts[i])
+        exp = 0 if i in bad else oracle_counts(host[st:st + n * k // 8], n, k)
+        assert (got[i, :k] == exp).all(), f"stream {i}"
+        assert (got[i, k:] == 0).all()
 
 
 def test_static_capacity_is_reported_before_launch():
