@@ -195,6 +195,29 @@ def test_one_huge_stream_over_all_blocks():
         bt.check()
 
 
+@pytest.mark.timeout(600)
+def test_stream_over_4_gib_in_a_batch():
+    """A stream of 2^32 + 7 uint8 words (its word count and its bytes both past 32
+    bits) at an odd address, between small streams of the other widths: at the
+    default shape and at one block per compute unit, where a block's share of the
+    long stream is largest; every stream against the oracle in full."""
+    lengths = np.array([1000, (1 << 32) + 7, 77, 5], np.uint64)
+    ks = np.array([16, 8, 32, 8], np.int32)
+    s = I.StreamSet(lengths, ks, np.array([0.5, 0.5, 0.02, 0.9]))
+    bt = Batch(s, SEED + 70, threads=I.default_threads())
+    assert int(bt.starts[1]) % 16 == 7  # the seed places the long stream at an odd address
+    for cfg in (None, dict(blocks_per_cu=1, block_threads=64)):
+        bt.counts.zero_()
+        plan = B.Plan(len(lengths))
+        if cfg:
+            plan.config = cfg
+        say(f"stream over 4 GiB in a batch, cfg={cfg}")
+        plan.run(bt.descs)
+        torch.cuda.synchronize()
+        plan.close()
+        bt.check()
+
+
 def test_autotune_leaves_counts_and_picks_valid_config(small_batch, tmp_path):
     b = small_batch
     b.counts.zero_()
