@@ -110,6 +110,18 @@ const EnvBatch& env_batch();
 bool parse_kv(const char* text, int (*apply)(void* ctx, const char* key, const char* value),
               void* ctx);
 
+// Blocks a launch needs for `tiles` wave tiles with `wpb` waves per block: at least
+// two tiles per wave, both in flight at once.  Every block ends with one atomic per
+// counter on the same few counters, and those atomics serialise, so on a small input
+// one tile per wave costs more in flushes than it saves in latency: 2 MiB of uint16
+// words took 4.3 us per back-to-back call on 128 four-wave blocks (one tile each),
+// 3.7 us on 64 (two each), 3.75 us on 32 (four each).  Large inputs are unaffected:
+// their grids stop at the blocks that fit on the chip.
+inline uint64_t blocks_needed(uint64_t tiles, int wpb) {
+    const uint64_t per = 2 * (uint64_t)wpb;
+    return (tiles + per - 1) / per;
+}
+
 // log2 of a circuit depth of 4, 8, 16 or 32 dwords per lane; -1 for any other.
 inline int logd_of_depth(int depth) {
     return depth == 4 ? 2 : depth == 8 ? 3 : depth == 16 ? 4 : depth == 32 ? 5 : -1;

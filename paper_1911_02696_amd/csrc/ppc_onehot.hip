@@ -382,7 +382,7 @@ static int launch_histogram(const void* ids, uint64_t n, int id_bytes, int bins,
     const Split s = split_stream(ids, nbytes, 8);
     const int wpb = threads / kWave;
     const uint64_t tiles = (s.units + kWave * 4 - 1) / (kWave * 4);
-    uint64_t need = (tiles + wpb - 1) / wpb;
+    uint64_t need = blocks_needed(tiles, wpb);
     if (need == 0) need = 1;
     int64_t grid;
     if (c.grid > 0) {

@@ -279,7 +279,7 @@ int resolve_launch(const ppc_launch_config* cfg, int k, uint64_t units, bool has
     const uint64_t tile_units =
         c.variant == PPC_VARIANT_BALLOT ? (uint64_t)kWave : (uint64_t)kWave * ((1u << logd) / 4);
     const uint64_t tiles = (units + tile_units - 1) / tile_units;
-    uint64_t need = (tiles + wpb - 1) / wpb;
+    uint64_t need = blocks_needed(tiles, wpb);
     if (need == 0) need = has_edges ? 1 : 0;
     int64_t grid;
     if (c.grid > 0) {

@@ -172,7 +172,7 @@ int launch_wide64(const void* ptr, uint64_t n, uint64_t* counts, ppc_stream stre
     const int wpb = sh.threads / kWave;
     const uint64_t tile_units = (uint64_t)kWave * (uint64_t)(sh.depth / 4);
     const uint64_t tiles = (s.units + tile_units - 1) / tile_units;
-    uint64_t need = (tiles + wpb - 1) / wpb;
+    uint64_t need = blocks_needed(tiles, wpb);
     if (need == 0) need = 1;
     int64_t grid = (cfg && cfg->grid > 0) ? cfg->grid : (int64_t)sh.bpc * dev->cus;
     if (!(cfg && cfg->grid > 0) && (uint64_t)grid > need) grid = (int64_t)need;
@@ -226,7 +226,7 @@ static int launch_planes16(const void* const* planes, uint32_t m, uint64_t n, ui
     // The chip's blocks are shared out over the planes (all of a length).
     const int wpb = sh.threads / kWave;
     const uint64_t tile_units = (uint64_t)kWave * (uint64_t)(sh.depth / 4);
-    uint64_t need = ((units_max + tile_units - 1) / tile_units + wpb - 1) / wpb;
+    uint64_t need = blocks_needed((units_max + tile_units - 1) / tile_units, wpb);
     if (need == 0) need = 1;
     int64_t per;
     if (cfg && cfg->grid > 0) {
