@@ -1,12 +1,14 @@
-"""The single-stream, wide-word and histogram entry points allocate nothing and
-enqueue only kernels on the caller's stream, so they can be captured into a HIP
-graph: a captured sequence, replayed several times with eager work and
-synchronisations in between, adds exactly one eager pass per replay each time."""
+"""The single-stream, wide-word and histogram entry points, and the allocation-free
+batched count, allocate nothing and enqueue only kernels on the caller's stream, so
+they can be captured into a HIP graph: a captured sequence, replayed several times
+with eager work and synchronisations in between, adds exactly one eager pass per
+replay each time."""
 import numpy as np
 import pytest
 import torch
 
 from paper_1911_02696_amd import api
+from paper_1911_02696_amd import batch as B
 from paper_1911_02696_amd import inputs as I
 
 from gpu_util import counts_np, host_bytes, oracle_counts, say, to_device
@@ -65,3 +67,45 @@ def test_entry_points_replay_from_a_graph():
         for name, got, one, e in zip(("u16", "u64", "histogram", "planes"), outs, ref, eager):
             assert (counts_np(got) == r * one).all(), (name, r)
             assert (counts_np(e) == one).all(), (name, r)
+
+
+@pytest.mark.parametrize("m", [700, 5000])  # single-block and split preparation
+def test_static_batch_replays_from_a_graph(m):
+    """pospopcnt_batch_static captured after a first eager call (which looks up its
+    scratch array's address), replayed three times; between replays an eager call on
+    the same stream uses the same scratch array for another counts table."""
+    s = I.loguniform_streams(m, 14, SEED + 10 + m)
+    s.lengths[::37] = 0
+    nb = s.nbytes.astype(np.int64)
+    starts, size = I.batch_layout(nb, SEED + 10 + m)
+    host = np.zeros(size + 64, np.uint8)
+    I.fill_streams(host, s, starts, SEED + 10 + m)
+    dev = torch.from_numpy(host).cuda()
+    tables = []
+    for _ in range(2):
+        counts = torch.zeros((m, 32), dtype=torch.int64, device="cuda")
+        d = B.descriptors(dev.data_ptr() + starts, s.lengths, s.ks,
+                          counts.data_ptr() + 256 * np.arange(m))
+        tables.append((counts, B.to_device(d)))
+    (c_graph, d_graph), (c_eager, d_eager) = tables
+    say(f"graph: static batch m={m}, eager reference")
+    B.batch_static(d_eager)
+    torch.cuda.synchronize()
+    one = c_eager.cpu().numpy().copy()
+    for i in range(0, m, max(1, m // 40)):
+        k, n, st = int(s.ks[i]), int(s.lengths[i]), int(starts[i])
+        assert (one[i, :k] == oracle_counts(host[st:st + n * k // 8], n, k)).all(), i
+    g = torch.cuda.CUDAGraph()
+    say(f"graph: static batch m={m}, capture")
+    with torch.cuda.graph(g):
+        B.batch_static(d_graph)
+    torch.cuda.synchronize()
+    assert (c_graph.cpu().numpy() == 0).all()  # capture alone runs nothing
+    for r in range(1, 4):
+        say(f"graph: static batch m={m}, replay {r}")
+        g.replay()
+        c_eager.zero_()
+        B.batch_static(d_eager)  # the same scratch array, between replays
+        torch.cuda.synchronize()
+        assert (c_graph.cpu().numpy() == r * one).all(), r
+        assert (c_eager.cpu().numpy() == one).all(), r
