@@ -69,11 +69,14 @@ def test_entry_points_replay_from_a_graph():
             assert (counts_np(e) == one).all(), (name, r)
 
 
+@pytest.mark.parametrize("form", ["static", "plan"])
 @pytest.mark.parametrize("m", [700, 5000])  # single-block and split preparation
-def test_static_batch_replays_from_a_graph(m):
-    """pospopcnt_batch_static captured after a first eager call (which looks up its
-    scratch array's address), replayed three times; between replays an eager call on
-    the same stream uses the same scratch array for another counts table."""
+def test_batch_replays_from_a_graph(m, form):
+    """The batched count captured into the caller's graph after a first eager call:
+    pospopcnt_batch_static (whose first call looks up its scratch array's address), or
+    pospopcnt_batch on a plan made without its own graph.  Replayed three times; between
+    replays an eager call on the same stream uses the same scratch for another counts
+    table."""
     s = I.loguniform_streams(m, 14, SEED + 10 + m)
     s.lengths[::37] = 0
     nb = s.nbytes.astype(np.int64)
@@ -88,24 +91,32 @@ def test_static_batch_replays_from_a_graph(m):
                           counts.data_ptr() + 256 * np.arange(m))
         tables.append((counts, B.to_device(d)))
     (c_graph, d_graph), (c_eager, d_eager) = tables
-    say(f"graph: static batch m={m}, eager reference")
-    B.batch_static(d_eager)
+    if form == "static":
+        run = B.batch_static
+    else:
+        plan = B.Plan(m)
+        run = plan.run
+    say(f"graph: {form} batch m={m}, eager reference")
+    run(d_eager)
     torch.cuda.synchronize()
     one = c_eager.cpu().numpy().copy()
     for i in range(0, m, max(1, m // 40)):
         k, n, st = int(s.ks[i]), int(s.lengths[i]), int(starts[i])
         assert (one[i, :k] == oracle_counts(host[st:st + n * k // 8], n, k)).all(), i
     g = torch.cuda.CUDAGraph()
-    say(f"graph: static batch m={m}, capture")
+    say(f"graph: {form} batch m={m}, capture")
     with torch.cuda.graph(g):
-        B.batch_static(d_graph)
+        run(d_graph)
     torch.cuda.synchronize()
     assert (c_graph.cpu().numpy() == 0).all()  # capture alone runs nothing
     for r in range(1, 4):
-        say(f"graph: static batch m={m}, replay {r}")
+        say(f"graph: {form} batch m={m}, replay {r}")
         g.replay()
         c_eager.zero_()
-        B.batch_static(d_eager)  # the same scratch array, between replays
+        run(d_eager)  # the same scratch, between replays
         torch.cuda.synchronize()
         assert (c_graph.cpu().numpy() == r * one).all(), r
         assert (c_eager.cpu().numpy() == one).all(), r
+    del g
+    if form == "plan":
+        plan.close()
