@@ -244,7 +244,11 @@ int ppc_plan_destroy(ppc_plan* plan);
  * call for a given (d_descs, m, configuration) and replayed by later calls; the
  * graph reads the descriptors when it runs, so their contents may change between
  * calls.  Calls sharing a plan must not overlap in time (the plan's scratch is
- * reused); use one plan per concurrent stream.  m = 0 is a no-op.
+ * reused); use one plan per concurrent stream.  To record the call into a graph of
+ * the caller's own (stream capture), use a plan made without PPC_PLAN_GRAPH: the
+ * call then only enqueues kernels, which read the plan's scratch when the graph
+ * runs, so the plan must outlive the graph and its replays count as calls on the
+ * plan.  m = 0 is a no-op.
  * Errors: PPC_ERR_NULL, PPC_ERR_ALIGN, PPC_ERR_ARG (m > max_streams), PPC_ERR_HIP. */
 int pospopcnt_batch(ppc_plan* plan, const ppc_desc* d_descs, uint32_t m, ppc_stream stream);
 
