@@ -41,15 +41,6 @@ struct Codes {
     // Input bits that are zero in every input dword whose ids are all < C.
     static constexpr uint32_t BAD = LANE * (IDMASK & ~(uint32_t)(C - 1));
 
-    // Lanes of ids >= C, all ones per such id.  Per lane the high id bits, moved
-    // down, are at most 31 (bytes) or 0x1FFF (halves), so adding 0x7F / 0x7FFF
-    // sets the lane's top bit exactly for a nonzero value and never carries into
-    // the next lane.
-    __device__ static __forceinline__ uint32_t dead_ids(uint32_t x) {
-        const uint32_t top = IDB == 1 ? 0x80808080u : 0x80008000u;
-        const uint32_t z = (((x & BAD) >> LOGC) + (top - LANE)) & top;
-        return z | (z - (z >> (IDB == 1 ? 7 : 15)));
-    }
 
     // The masked path: a tile that may hold ids >= C, or dwords that are not
     // input (unit[i] false: the missing units of a partial tile).  Those ids must
@@ -62,14 +53,17 @@ struct Codes {
     //   an id >= 8 (0x00, or 0xFF: one in every class).  A u16 id whose high byte
     //   is not zero is cleared by the mask table below applied to its high byte.
     //   Bits 0 and 1 both set mark exactly the 0xFF bytes; *ph counts them.
-    // - C = 16, 32 (clear_ids, then make): each id gets a mask of all ones when it
-    //   is >= C, and masked ids become id 0 in place, whose code lands in class 0;
-    //   *ph adds the mask's popcount, 8 per such u8 id and 16 per u16 id.  For u8
-    //   ids a byte table gives the mask bytes (table {0xFFFFFFFF : 0xFFFFFF00}:
-    //   0x00 at index 0, 0xFF elsewhere), indexed by the id's bits above LOGC: bits
-    //   5..7 for C = 32; bits 4..7 for C = 16, with bit 3 of the index also set in
-    //   bit 0 so that selector 12, which gives zero, never occurs and 8..11 copy
-    //   the sign of a 0xFF byte.  For u16 ids dead_ids gives the mask halves.
+    // - C = 16, 32 (clear_ids, then make): every id >= C becomes id 0 in place,
+    //   whose code lands in class 0.  For u8 ids a byte table gives a mask of all
+    //   ones per such id (table {0xFFFFFFFF : 0xFFFFFF00}: 0x00 at index 0, 0xFF
+    //   elsewhere), indexed by the id's bits above LOGC: bits 5..7 for C = 32; bits
+    //   4..7 for C = 16, with bit 3 of the index also set in bit 0 so that selector
+    //   12, which gives zero, never occurs and 8..11 copy the sign of a 0xFF byte;
+    //   *ph adds the mask's popcount, 8 per such id.  For u16 ids one packed
+    //   16-bit minimum clamps each id to C: an id < C keeps its value, which has
+    //   bit LOGC clear, and an id >= C becomes C, which has only bit LOGC set, so
+    //   that bit counts the stand-ins (*ph adds one per such id) and keeping the
+    //   bits below LOGC turns them into id 0.
     static constexpr bool CLEARS_IDS = C != 8;
 
     __device__ static __forceinline__ void make_masked(uint32_t* code, const uint32_t* in,
@@ -103,12 +97,23 @@ struct Codes {
 
     __device__ static __forceinline__ void clear_ids(uint32_t* in, const bool* unit,
                                                      uint32_t* ph) {
+        if constexpr (IDB == 2) {
+            typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+            const u16x2 cc = {(unsigned short)C, (unsigned short)C};
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) {
+                uint32_t cl = __builtin_bit_cast(
+                    uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, in[i]), cc));
+                cl = unit[i] ? cl : LANE * C;  // a missing unit: two stand-ins
+                *ph += (uint32_t)__builtin_popcount(cl & (LANE * C));
+                in[i] = cl & (LANE * (C - 1));
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < NIN; ++i) {
             uint32_t m;
-            if constexpr (IDB == 2) {
-                m = dead_ids(in[i]);
-            } else if constexpr (C == 32) {
+            if constexpr (C == 32) {
                 m = __builtin_amdgcn_perm(0xFFFFFFFFu, 0xFFFFFF00u, (in[i] >> 5) & 0x07070707u);
             } else {
                 const uint32_t h = (in[i] >> 4) & 0x0F0F0F0Fu;
@@ -125,8 +130,10 @@ struct Codes {
         if constexpr (C == 8) {
 #pragma unroll
             for (int i = 0; i < C; ++i) tot[i] -= ph;
+        } else if constexpr (IDB == 2) {
+            tot[0] -= ph;  // one per stand-in id
         } else {
-            tot[0] -= ph / (8 * IDB);
+            tot[0] -= ph / 8;  // eight mask bits per stand-in id
         }
     }
 
