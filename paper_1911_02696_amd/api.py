@@ -30,15 +30,17 @@ def stream_handle(stream=None) -> int:
     return int(stream)
 
 
-def _launch_on(stream, fresh) -> int:
-    """The stream handle to launch on, on the current device.  `fresh` is a tensor
-    this binding has just filled on torch's current stream (None if the caller
-    supplied the output): a launch on another stream first waits for that fill,
-    and the tensor is marked as used by that stream, so that its memory is not
-    handed out again before the launch ends."""
+def _launch_on(stream, fresh, device: int | None = None) -> int:
+    """The stream handle to launch on, on the current device (`device`: its index,
+    when the caller already has it).  `fresh` is a tensor this binding has just
+    filled on torch's current stream (None if the caller supplied the output): a
+    launch on another stream first waits for that fill, and the tensor is marked as
+    used by that stream, so that its memory is not handed out again before the
+    launch ends."""
     if stream is None:
         # torch's current stream as a raw handle, without building a Stream object
-        return torch._C._cuda_getCurrentRawStream(torch.cuda.current_device())
+        return torch._C._cuda_getCurrentRawStream(
+            torch.cuda.current_device() if device is None else device)
     cur = torch.cuda.current_stream()
     if isinstance(stream, torch.cuda.Stream):
         if fresh is not None and stream != cur:
@@ -71,11 +73,13 @@ def _device_bytes(x: torch.Tensor, byte_offset: int) -> int:
 
 
 def _counts_tensor(out, k, device):
+    """`device`: a torch.device or a CUDA device index."""
     if out is None:
         return torch.zeros(k, dtype=torch.int64, device=device)
     if out.dtype not in (torch.int64, torch.uint64) or out.numel() != k:
         raise ValueError(f"out must hold {k} int64 counters")
-    if not out.is_contiguous() or out.device != device:
+    index = device if isinstance(device, int) else device.index
+    if not out.is_contiguous() or not out.is_cuda or out.get_device() != index:
         raise ValueError("out must be contiguous and on the input's device")
     return out
 
@@ -103,16 +107,20 @@ def pospopcnt(x: torch.Tensor, k: int, n: int | None = None, byte_offset: int = 
         n = avail // (k // 8)
     if n < 0 or n * (k // 8) > avail:
         raise ValueError(f"{n} words of {k} bits do not fit in {avail} bytes")
+    dev = x.get_device()
     fresh = out is None
-    out = _counts_tensor(out, k, x.device)
-    cfg = launch_config(**config) if config else None
-    if x.device.index == torch.cuda.current_device():  # no device switch needed
-        s = _launch_on(stream, out if fresh else None)
-        pospopcnt_ptr(x.data_ptr() + byte_offset, n, k, out.data_ptr(), s, cfg)
-        return out
-    with torch.cuda.device(x.device):
-        s = _launch_on(stream, out if fresh else None)
-        pospopcnt_ptr(x.data_ptr() + byte_offset, n, k, out.data_ptr(), s, cfg)
+    out = _counts_tensor(out, k, dev)
+    cfg = ctypes.byref(launch_config(**config)) if config else None
+    cur = torch.cuda.current_device()
+    if dev == cur:  # no device switch needed
+        st = L.lib().pospopcnt_ex(x.data_ptr() + byte_offset, n, k, out.data_ptr(),
+                                  _launch_on(stream, out if fresh else None, cur), cfg)
+    else:
+        with torch.cuda.device(dev):
+            st = L.lib().pospopcnt_ex(x.data_ptr() + byte_offset, n, k, out.data_ptr(),
+                                      _launch_on(stream, out if fresh else None), cfg)
+    if st:
+        raise PpcError(st, f"pospopcnt(k={k}, n={n})")
     return out
 
 
